@@ -1,0 +1,221 @@
+/*
+ * pat.h -- C ABI of the MI355X (gfx950) photoacoustic-tomography hot path.
+ *
+ * Method: Arridge, Beard, Betcke, Cox, Huynh, Lucka, Ogunlade, Zhang,
+ * "Accelerated high-resolution photoacoustic tomography via compressed
+ * sensing" (arXiv 1605.00133). The library computes
+ *
+ *   f = C A p0                     measurement model, eq. (Fwd), Sec. 4.1
+ *   p = A^T C^T f                  back-projection / gradient, eq. (BP), Sec. 4.4
+ *   q = prox_{TV + (q>=0), alpha}  positivity-constrained TV denoising, eq. (Prox), App. A/B
+ *   p = argmin 1/2||CAp - f||^2 + lambda TV(p), p >= 0   eq. (VarReg)/(TV+), by FISTA (App. B)
+ *       optionally enhanced by Bregman iterations, eq. (BregIterA/B), Sec. 4.5
+ *
+ * where A is 3D linear acoustic propagation of the initial pressure
+ * (eq. PATfwd) by a k-space pseudospectral scheme with a perfectly matched
+ * layer, sampled on the detection plane z = 0 at every time step (Sec. 4.3),
+ * and C is the sub-sampling operator: every plane pixel, random single
+ * points (rSP) or scrambled +-1 Hadamard patterns (sHd) (Sec. 3.1, 4.3).
+ *
+ * Conventions shared by every entry point
+ *  - Volumes are float32 arrays [nz][ny][nx] (x fastest); the detection plane
+ *    is the slab z = 0. Data arrays are float32 [nt][mc] (time-major).
+ *  - Pointers named "device" are HIP device pointers; all other pointers are
+ *    host pointers. The caller owns every buffer it passes; the library never
+ *    frees caller memory.
+ *  - Work is enqueued asynchronously on the plan's HIP stream unless the entry
+ *    point returns a host value (those synchronise the stream).
+ *  - Every call returns a pat_status and never aborts; pat_last_error() gives
+ *    a message for the last non-OK status of the calling thread. Arguments
+ *    are validated before any work is enqueued.
+ *  - Results are deterministic: no floating-point atomics, fixed reduction
+ *    trees (FP64 partial sums for every reported scalar).
+ *  - Concurrent calls on one plan are not allowed (the plan's workspace is
+ *    shared by all its entry points); distinct plans are independent.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAT_OK = 0,
+  PAT_ERR_INVALID = 1,      /* bad argument: null pointer, size, range */
+  PAT_ERR_UNSUPPORTED = 2,  /* valid but not built: grid size, non power-of-two Hadamard plane */
+  PAT_ERR_NOMEM = 3,        /* workspace too small or a table allocation failed */
+  PAT_ERR_HIP = 4,          /* HIP runtime or launch error */
+  PAT_ERR_NONFINITE = 5     /* a reported scalar is NaN or Inf */
+} pat_status;
+
+/* Discretisation (Table 2 lists the paper's values). The FFT grid includes
+ * the PML: pml_size cells on each side in x and y, and a 2*pml_size slab at
+ * the top of z (z in [nz - 2 pml, nz)), so the plane z = 0 sits directly in
+ * front of it. nx, ny, nz must each be one of the built sizes (16, 32, 64,
+ * 128) and nt >= 1. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx;          /* voxel size [m], isotropic */
+  double c0;          /* homogeneous sound speed [m/s] */
+  double rho0;        /* ambient density; A does not depend on it (> 0) */
+  double dt;          /* time step = temporal sampling interval [s] */
+  int32_t nt;         /* samples at t = 0, dt, ..., (nt-1) dt */
+  int32_t pml_size;   /* P >= 0, 2P < min(nx, ny) and 2P < nz */
+  double pml_alpha;   /* absorption sigma = alpha (c0/dx) d^4, d in [0,1] */
+} pat_grid;
+
+typedef enum {
+  PAT_SAMPLE_FULL = 0,      /* conventional scan: every plane pixel, mc = nx*ny */
+  PAT_SAMPLE_POINTS = 1,    /* rSP: idx = mc sorted distinct pixel ids iy*nx+ix */
+  PAT_SAMPLE_HADAMARD = 2   /* sHd: f_j = (W x~)[idx_j] / sqrt(nx*ny), x~[q] = s[perm[q]] */
+} pat_sample_kind;
+
+/* Sub-sampling operator C (Sec. 3.1, 4.3). idx and perm are HOST arrays and
+ * are copied into the plan. POINTS: idx[mc] strictly increasing in
+ * [0, nx*ny). HADAMARD: nx*ny a power of two, perm[nx*ny] a permutation,
+ * idx[mc] strictly increasing Sylvester-Walsh row ids. C C^T = I for all kinds. */
+typedef struct {
+  int32_t kind;               /* pat_sample_kind */
+  int32_t mc;                 /* rows of f per time step */
+  const int32_t* idx;         /* host; NULL for FULL */
+  const int32_t* perm;        /* host; HADAMARD only */
+} pat_sampling;
+
+typedef struct pat_plan pat_plan;
+
+/* Bytes of device workspace a plan needs (state fields, spectra, the plane
+ * time series and the solver vectors). Returns 0 for invalid arguments. */
+size_t pat_plan_workspace_bytes(const pat_grid* grid, const pat_sampling* smp);
+
+/* Create a plan: validates grid and sampling, uploads the small tables
+ * (twiddles, wavenumbers, PML factors, index maps) and carves `workspace`
+ * (device, >= pat_plan_workspace_bytes, 256-byte aligned, caller-owned and
+ * kept alive until pat_plan_destroy). stream: a hipStream_t or NULL. */
+pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* stream,
+                           void* workspace, size_t workspace_bytes, pat_plan** out);
+pat_status pat_plan_destroy(pat_plan* plan);
+pat_status pat_plan_set_stream(pat_plan* plan, void* stream);
+
+/* f = C A p0 (eq. Fwd without noise). p0: device [nz][ny][nx]; f: device [nt][mc].
+ * p0 and f must not overlap. */
+pat_status pat_forward(pat_plan* plan, const float* p0, float* f);
+
+/* p = A^T C^T f, the exact transpose of pat_forward's arithmetic (eq. BP).
+ * f: device [nt][mc]; p: device [nz][ny][nx]; no overlap. */
+pat_status pat_adjoint(pat_plan* plan, const float* f, float* p);
+
+/* C alone on a plane series s: device [nt][ny][nx] -> f: device [nt][mc]. */
+pat_status pat_sample(pat_plan* plan, const float* s, float* f);
+/* C^T alone: f: device [nt][mc] -> s: device [nt][ny][nx]. */
+pat_status pat_sample_adjoint(pat_plan* plan, const float* f, float* s);
+
+/* Floats of the PDHG dual for pat_tv_prox: bc = 0 (Neumann) 3*nx*ny*nz laid
+ * out [3][nz][ny][nx]; bc = 1 (Dirichlet) 3*(nx+1)*(ny+1)*(nz+1) laid out
+ * [3][nz+1][ny+1][nx+1] over the zero-padded grid's points 0..n (components x, y, z). */
+size_t pat_tv_dual_floats(const pat_grid* grid, int32_t bc);
+
+/* q = argmin_{q >= 0} 1/2||q - v||^2 + alpha TV(q) by n_iter iterations of the
+ * accelerated primal-dual hybrid gradient method (App. B), q started at
+ * max(0, v), step sizes 1/sqrt(12). TV is isotropic forward differences with
+ * Neumann (bc = 0) or Dirichlet (bc = 1, jumps to zero at the faces added)
+ * boundaries (App. A). v, q: device volumes, may alias. dual: device,
+ * pat_tv_dual_floats(bc) floats, in/out warm start (zero it for a cold start). */
+pat_status pat_tv_prox(pat_plan* plan, const float* v, float* q, float alpha, int32_t n_iter,
+                       int32_t bc, float* dual);
+
+/* TV(p) (App. A) as an FP64 host value; syncs. */
+pat_status pat_tv_norm(pat_plan* plan, const float* p, int32_t bc, double* out);
+
+/* Largest eigenvalue of A^T C^T C A by n_iter power steps from x0 (device
+ * volume, not modified): x <- x0/|x0|; repeat w = A^T C^T C A x, L = |w|,
+ * x = w/L. Used for the step size eta = 1.8/L (App. B). Host result; syncs. */
+pat_status pat_power_iteration(pat_plan* plan, const float* x0, int32_t n_iter, double* L_out);
+
+typedef struct {
+  double lambda;          /* TV weight */
+  double L;               /* Lipschitz estimate of A^T C^T C A; eta = 1.8 / L */
+  int32_t n_outer;        /* Bregman iterations (1 = plain TV+) */
+  int32_t n_inner;        /* FISTA iterations per outer step */
+  int32_t n_prox;         /* PDHG iterations per prox */
+  int32_t bc;             /* TV boundary: 0 Neumann, 1 Dirichlet */
+  int32_t restart;        /* 1: restart + backtracking on energy increase */
+  int32_t max_backtrack;  /* halvings after the plain gradient step (paper: 5) */
+  const float* p_ref;     /* optional device volume for PSNR logging, or NULL */
+} pat_recon_params;
+
+/* Per-FISTA-iteration log, host buffers owned by the caller, each with
+ * `capacity` entries (any pointer may be NULL). Entry i is iteration i of the
+ * flattened outer x inner loop. flags: 0 plain step, 1 + j restart that kept
+ * the step after j halvings. residual: ||C A x - d||; energy: 1/2 residual^2 +
+ * lambda TV(x); bregman_residual (per outer step): ||C A p^k - f||. */
+typedef struct {
+  int32_t capacity;
+  int32_t n_log;          /* out: entries written */
+  double* energy;
+  double* residual;
+  double* tv;
+  int32_t* flags;
+  double* psnr;           /* needs p_ref */
+  double* t_ms;           /* wall time since the call started, after the iteration */
+  double* bregman_residual; /* n_outer entries */
+} pat_recon_report;
+
+/* TV+ (n_outer = 1) or TV+Br reconstruction of p from f (device [nt][mc]) into p
+ * (device volume). Syncs once per FISTA iteration to read the FP64 energy. */
+pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p,
+                           const pat_recon_params* params, pat_recon_report* report);
+
+/* Thresholded PSNR of p against p_ref (eq. PSNR) over the non-PML interior with
+ * z >= 1: negatives clipped, both scaled by their maximum, values < 0.1 zeroed.
+ * p, p_ref: device volumes. Host result; syncs. +Inf when identical. */
+pat_status pat_psnr(pat_plan* plan, const float* p, const float* p_ref, double* out);
+
+/* Diagnostics: HIP-event timing of the propagator's kernels, for roofline
+ * reporting. Between pat_profile_begin and pat_profile_end every launch of
+ * kernel `kernel_id` (or of all of them, kernel_id = -2) made by pat_forward,
+ * pat_adjoint and the solvers on this plan is bracketed by two events on the
+ * plan's stream, up to max_launches launches. pat_profile_end syncs and fills
+ * total_ms[PAT_K_COUNT] and launches[PAT_K_COUNT] (host, either may be NULL). */
+typedef enum {
+  PAT_K_ZGRAD = 0,      /* forward: z pass of the gradient (1 spectrum in, 2 out) */
+  PAT_K_FWD_U = 1,      /* forward: slab pass, velocity update and its 2D FFT (per component) */
+  PAT_K_ZDIV = 2,       /* forward: z pass of the divergences (per component) */
+  PAT_K_FWD_RHO = 3,    /* forward: slab pass, density update, pressure, sensor plane, 2D FFT */
+  PAT_K_ZGRAD_ADJ = 4,  /* adjoint: z pass of the gradients (per component) */
+  PAT_K_ADJ_U = 5,      /* adjoint: slab pass, velocity update and its 2D FFT (per component) */
+  PAT_K_ZDIV_SUM = 6,   /* adjoint: z pass of the summed divergence (3 in, 1 out) */
+  PAT_K_ADJ_RHO = 7,    /* adjoint: slab pass, density update with the data source, 2D FFT */
+  PAT_K_COUNT = 8
+} pat_kernel_id;
+
+pat_status pat_profile_begin(pat_plan* plan, int32_t kernel_id, int32_t max_launches);
+pat_status pat_profile_end(pat_plan* plan, double* total_ms, int32_t* launches);
+
+/* Name and algorithmic HBM bytes per launch of a kernel on this plan's grid:
+ * every field a launch must read or write once (slab spectra of
+ * nz*(nx/2+1)*ny complex floats, real fields of nx*ny*nz floats, the sensor
+ * plane). *name points to static storage. */
+pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char** name, double* bytes_per_launch);
+
+/* Host-only index generators (no GPU needed). SplitMix64(seed) drives a
+ * Durstenfeld Fisher-Yates shuffle of [0, n_pix) with unbiased rejection draws.
+ * rSP: the first mc entries, sorted ascending. sHd: perm = shuffle(seed), rows =
+ * first mc entries of shuffle(seed + 1), sorted; n_pix must be a power of two. */
+pat_status pat_make_rsp_mask(int32_t n_pix, int32_t mc, uint64_t seed, int32_t* idx_out);
+pat_status pat_make_shd_pattern(int32_t n_pix, int32_t mc, uint64_t seed,
+                                int32_t* perm_out, int32_t* rows_out);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* pat_last_error(void);
+
+/* Library version string. */
+const char* pat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAT_H */

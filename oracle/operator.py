@@ -31,8 +31,13 @@ from .grid import wavenumbers, kappa_grid, pml_factors
 
 
 def _workers():
+    """FFT threads: the host's cores, capped by OMP_NUM_THREADS when it is set."""
     import os
-    return max(1, os.cpu_count() or 1)
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
 
 
 class WaveOperator:

@@ -1,0 +1,89 @@
+// Shared definitions of the wave propagator (host plan <-> kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace pat {
+
+// Device tables of one grid, built in FP64 on the host and rounded once.
+// Spectral arrays use the slab-spectrum layout [z][kx][ky_pos]:
+//   kx in [0, nx/2] natural order (half spectrum of the real x transform),
+//   ky_pos = position of ky after the forward y transform (digit-reversed),
+//   and in the z-pencil kernels kz_pos likewise for z.
+struct WaveTables {
+  const float2* tw_mx;   // exp(-2 pi i j / (nx/2)), j < nx/2
+  const float2* tw_nx;   // exp(-2 pi i k / nx),     k <= nx/2
+  const float2* tw_y;    // exp(-2 pi i j / ny),     j < ny
+  const float2* tw_z;    // exp(-2 pi i j / nz),     j < nz
+  const float2* mpx;     // i kx exp(+i kx dx/2), indexed by kx
+  const float2* mmx;     // i kx exp(-i kx dx/2)
+  const float2* mpy;     // same for y, indexed by ky_pos
+  const float2* mmy;
+  const float2* mpz;     // same for z, indexed by kz_pos
+  const float2* mmz;
+  const float* hx;       // (c0 dt / 2) kx   (argument scale of the k-space sinc)
+  const float* hy;       // by ky_pos
+  const float* hz;       // by kz_pos
+  const float* ax;       // PML factor at staggered points i + 1/2
+  const float* ay;
+  const float* az;
+  const float* bx;       // PML factor at collocated points i
+  const float* by;
+  const float* bz;
+};
+
+struct WaveScalars {
+  float dt_over_rho0;    // dt / rho0
+  float dt_rho0;         // dt * rho0
+  float c2;              // c0^2
+  float inv_3c2;         // 1 / (3 c0^2)
+  float half_dt_over_rho0;  // dt / (2 rho0)
+  float inv_ntot;        // 1 / (nx ny nz): normalisation of an FFT round trip
+};
+
+// Launch helpers implemented per grid size in wave_kernels.hip.
+struct WaveBuffers {
+  float* u[3];           // velocity components (staggered), [nz][ny][nx]
+  float* rho[3];         // split density components
+  float2* spec[4];       // slab spectra [nz][nx/2+1][ny]
+};
+
+// Kernels of one time step, for per-kernel timing.
+enum KernelId {
+  K_ZGRAD = 0,      // forward pencil pass of the gradient (1 spectrum in, 2 out)
+  K_FWD_U = 1,      // forward slab pass: velocity update + R2C (per component)
+  K_ZDIV = 2,       // forward pencil pass of the divergences (per component)
+  K_FWD_RHO = 3,    // forward slab pass: density update, p, sensor plane, R2C of p
+  K_ZGRAD_ADJ = 4,  // adjoint pencil pass of the gradients (per component)
+  K_ADJ_U = 5,      // adjoint slab pass: velocity update + R2C (per component)
+  K_ZDIV_SUM = 6,   // adjoint pencil pass of the summed divergence (3 in, 1 out)
+  K_ADJ_RHO = 7,    // adjoint slab pass: density update + source + R2C (per component)
+  K_COUNT = 8
+};
+
+// Optional HIP-event bracketing of kernel launches (which = id, or -2 for all).
+struct KernelTimer {
+  int which;
+  hipEvent_t* ev;   // 2 per recorded launch
+  int* ids;         // kernel id of each recorded launch
+  int cap;
+  int count;
+};
+
+using WaveLaunchFwd = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
+                                     const float* p0, float* planes, int nt, hipStream_t, KernelTimer*);
+using WaveLaunchAdj = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
+                                     const float* planes, float* p, int nt, hipStream_t, KernelTimer*);
+
+struct WaveImpl {
+  int nx, ny, nz;
+  WaveLaunchFwd forward;
+  WaveLaunchAdj adjoint;
+};
+
+// Returns nullptr when the size is not built.
+const WaveImpl* find_wave_impl(int nx, int ny, int nz);
+
+}  // namespace pat

@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: exports, host index generators, validation."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.sampling import rsp_mask, shd_pattern
+from paper_1605_00133_amd import pat as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pat.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pat_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = P.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/pat.h but not exported"
+    assert set(names) == set(P.SIGNATURES), "binding and header disagree"
+
+
+def test_version_string():
+    assert b"gfx950" in P.lib().pat_version()
+
+
+@pytest.mark.parametrize("n_pix,mc", [(1024, 256), (16384, 2048)])
+def test_rsp_mask_bit_exact_with_oracle(n_pix, mc):
+    for seed in range(20):
+        assert np.array_equal(P.pat_make_rsp_mask(n_pix, mc, seed), rsp_mask(n_pix, mc, seed))
+
+
+@pytest.mark.parametrize("n_pix,mc", [(1024, 128), (16384, 2048)])
+def test_shd_pattern_bit_exact_with_oracle(n_pix, mc):
+    for seed in range(20):
+        perm, rows = P.pat_make_shd_pattern(n_pix, mc, seed)
+        operm, orows = shd_pattern(n_pix, mc, seed)
+        assert np.array_equal(perm, operm) and np.array_equal(rows, orows)
+
+
+def test_generators_reject_bad_arguments():
+    with pytest.raises(P.PatError) as e:
+        P.pat_make_rsp_mask(100, 101, 1)
+    assert e.value.status == 1
+    with pytest.raises(P.PatError) as e:
+        P.pat_make_shd_pattern(96 * 96, 10, 1)
+    assert e.value.status == 2
+
+
+def _grid(n=32, nt=190, pml=8):
+    return P.make_grid(n, n, n, 100e-6, 1500.0, 20e-9, nt, pml)
+
+
+def test_workspace_bytes_and_validation():
+    g = _grid()
+    full, _ = P.make_sampling("full", 32 * 32)
+    assert P.pat_plan_workspace_bytes(g, full) > 6 * 4 * 32 ** 3
+    bad_full, _ = P.make_sampling("full", 100)
+    assert P.pat_plan_workspace_bytes(g, bad_full) == 0
+    idx = np.array([3, 2, 9], dtype=np.int32)            # not increasing
+    bad_pts, keep = P.make_sampling("points", 3, idx)
+    assert P.pat_plan_workspace_bytes(g, bad_pts) == 0
+    assert P.pat_plan_workspace_bytes(_grid(n=48), full) == 0        # size not built
+    assert P.pat_plan_workspace_bytes(_grid(pml=16), full) == 0      # PML too thick
+    assert P.pat_plan_workspace_bytes(_grid(nt=0), full) == 0
+
+
+def test_plan_create_reports_validation_errors_without_gpu():
+    g = _grid()
+    perm = np.arange(32 * 32, dtype=np.int32)
+    perm[0] = 1                                         # not a permutation
+    smp, keep = P.make_sampling("hadamard", 4, np.array([0, 1, 2, 3], dtype=np.int32), perm)
+    h = C.c_void_p()
+    st = P.lib().pat_plan_create(C.byref(g), C.byref(smp), None, None, 0, C.byref(h))
+    assert st == 1 and b"permutation" in P.lib().pat_last_error()
+    assert not h.value
+
+
+def test_tv_dual_floats():
+    g = _grid()
+    assert P.pat_tv_dual_floats(g, "neumann") == 3 * 32 ** 3
+    assert P.pat_tv_dual_floats(g, "dirichlet") == 3 * 33 ** 3

@@ -1,0 +1,149 @@
+"""GPU (gfx950) parity of A, A^T and C against the FP64 oracle, through the C ABI.
+
+Tolerances (stated per result): A and A^T within 1e-5 relative L2 of FP64;
+index arrays bit-exact; the sampling operators alone within FP32 rounding.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.sampling import apply_c, apply_ct
+from gpu_cases import (empty, gaussian_data, gaussian_volume, gpu_plan, oracle_grid, oracle_sampling, phantom,
+                       rel_l2, to_dev, to_host)
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-5
+
+
+def _fwd_case(n, nt, kind, pml=8, x=None):
+    g = oracle_grid(n, nt, pml)
+    smp = oracle_sampling(kind, n)
+    x = phantom(n, pml) if x is None else x
+    ref = apply_c(oracle.WaveOperator(g).forward_planes(x), smp)
+    from paper_1605_00133_amd import pat as P
+    plan = gpu_plan(n, nt, smp, pml)
+    f = empty(plan.data_shape)
+    P.pat_forward(plan, to_dev(x), f)
+    return to_host(f), ref
+
+
+def _adj_case(n, nt, kind, pml=8, seed=5):
+    g = oracle_grid(n, nt, pml)
+    smp = oracle_sampling(kind, n)
+    y = gaussian_data((nt, smp.mc), seed)
+    ref = oracle.WaveOperator(g).adjoint_planes(apply_ct(y, smp, n, n))
+    from paper_1605_00133_amd import pat as P
+    plan = gpu_plan(n, nt, smp, pml)
+    p = empty(plan.vol_shape)
+    P.pat_adjoint(plan, to_dev(y), p)
+    return to_host(p), ref
+
+
+@pytest.mark.parametrize("n,nt,kind,pml", [(16, 40, "full", 4), (32, 190, "points", 8), (32, 190, "hadamard", 8),
+                                           (32, 190, "full", 8)])
+def test_forward_matches_oracle(n, nt, kind, pml):
+    got, ref = _fwd_case(n, nt, kind, pml)
+    err = rel_l2(got, ref)
+    print(f"forward {n}^3 nt={nt} {kind}: rel L2 vs FP64 = {err:.3e}")
+    assert err < TOL_OP
+
+
+@pytest.mark.parametrize("n,nt,kind,pml", [(16, 40, "full", 4), (32, 190, "points", 8), (32, 190, "hadamard", 8),
+                                           (32, 190, "full", 8)])
+def test_adjoint_matches_oracle(n, nt, kind, pml):
+    got, ref = _adj_case(n, nt, kind, pml)
+    err = rel_l2(got, ref)
+    print(f"adjoint {n}^3 nt={nt} {kind}: rel L2 vs FP64 = {err:.3e}")
+    assert err < TOL_OP
+
+
+def test_forward_without_pml_closed_form_random_input():
+    """P = 0 and white-noise p0 excite every mode including the Nyquist planes."""
+    n, nt = 32, 60
+    x = gaussian_volume((n, n, n), 3)
+    got, ref = _fwd_case(n, nt, "full", pml=0, x=x)
+    err = rel_l2(got, ref)
+    print(f"forward 32^3 no PML white noise: rel L2 = {err:.3e}")
+    assert err < TOL_OP
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_short_series_edge_cases(nt):
+    """Nt = 1 (no time step: plane of p0 only), 2 and 3, with a volume that is nonzero on the plane."""
+    x = gaussian_volume((32, 32, 32), 13)
+    got, ref = _fwd_case(32, nt, "points", x=x)
+    assert rel_l2(got, ref) < TOL_OP
+    got, ref = _adj_case(32, nt, "points")
+    assert rel_l2(got, ref) < TOL_OP
+
+
+def test_64_cubed_forward_adjoint():
+    got, ref = _fwd_case(64, 80, "hadamard")
+    e1 = rel_l2(got, ref)
+    got, ref = _adj_case(64, 80, "points")
+    e2 = rel_l2(got, ref)
+    print(f"64^3 nt=80: forward sHd {e1:.3e}, adjoint rSP {e2:.3e}")
+    assert e1 < TOL_OP and e2 < TOL_OP
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard", "full"])
+def test_gpu_adjoint_identity(kind):
+    """<C A x, y> = <x, A^T C^T y> on the GPU itself (FP32 arithmetic, FP64 dot products)."""
+    from paper_1605_00133_amd import pat as P
+    n, nt = 32, 120
+    smp = oracle_sampling(kind, n)
+    plan = gpu_plan(n, nt, smp)
+    x = gaussian_volume((n, n, n), 11)
+    y = gaussian_data((nt, smp.mc), 12)
+    f = empty(plan.data_shape)
+    p = empty(plan.vol_shape)
+    P.pat_forward(plan, to_dev(x), f)
+    P.pat_adjoint(plan, to_dev(y), p)
+    fh, ph = to_host(f), to_host(p)
+    lhs = float(np.vdot(fh, y))
+    rhs = float(np.vdot(x, ph))
+    # random vectors make <CAx, y> small by chance; scale by the Cauchy-Schwarz bound instead
+    scale = np.linalg.norm(fh) * np.linalg.norm(y)
+    rel = abs(lhs - rhs) / scale
+    print(f"GPU adjoint identity {kind}: |lhs-rhs|/(|CAx||y|) = {rel:.3e}, |lhs-rhs|/|lhs| = {abs(lhs - rhs) / abs(lhs):.3e}")
+    assert rel < 1e-6
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard", "full"])
+def test_sampling_operators_alone(kind):
+    from paper_1605_00133_amd import pat as P
+    n, nt = 32, 7
+    smp = oracle_sampling(kind, n)
+    plan = gpu_plan(n, nt, smp)
+    s = gaussian_data((nt, n, n), 21)
+    f = empty(plan.data_shape)
+    P.pat_sample(plan, to_dev(s), f)
+    ref = apply_c(s.astype(np.float32).astype(np.float64), smp)
+    got = to_host(f)
+    if kind == "hadamard":
+        assert rel_l2(got, ref) < 1e-6
+    else:
+        assert np.array_equal(got, ref)           # gathers move bits unchanged
+    r = gaussian_data((nt, smp.mc), 22)
+    s2 = empty(plan.plane_shape)
+    P.pat_sample_adjoint(plan, to_dev(r), s2)
+    ref = apply_ct(r.astype(np.float32).astype(np.float64), smp, n, n)
+    got = to_host(s2)
+    if kind == "hadamard":
+        assert rel_l2(got, ref) < 1e-6
+    else:
+        assert np.array_equal(got, ref)
+
+
+def test_operator_is_deterministic():
+    from paper_1605_00133_amd import pat as P
+    n, nt = 32, 100
+    smp = oracle_sampling("hadamard", n)
+    plan = gpu_plan(n, nt, smp)
+    x = to_dev(phantom(n))
+    a, b = empty(plan.data_shape), empty(plan.data_shape)
+    P.pat_forward(plan, x, a)
+    P.pat_forward(plan, x, b)
+    assert np.array_equal(to_host(a), to_host(b))

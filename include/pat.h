@@ -100,6 +100,13 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
 pat_status pat_plan_destroy(pat_plan* plan);
 pat_status pat_plan_set_stream(pat_plan* plan, void* stream);
 
+/* Arithmetic of the propagator's FFT butterflies: 64 (default) keeps FP64
+ * values in registers and LDS inside each transform pass and rounds to FP32
+ * once per pass; 32 computes in FP32 throughout (faster, about 5x larger
+ * rounding error, which accumulates over the Nt time steps). Stored fields
+ * and spectra are FP32 in both cases. */
+pat_status pat_plan_set_fft_precision(pat_plan* plan, int32_t bits);
+
 /* f = C A p0 (eq. Fwd without noise). p0: device [nz][ny][nx]; f: device [nt][mc].
  * p0 and f must not overlap. */
 pat_status pat_forward(pat_plan* plan, const float* p0, float* f);

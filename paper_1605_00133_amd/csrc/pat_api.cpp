@@ -128,15 +128,6 @@ double wavenumber(int m, int n, double dx) {
   return 2.0 * M_PI * (double)mm / ((double)n * dx);
 }
 
-float2 f2(double re, double im) { return make_float2((float)re, (float)im); }
-
-// i k exp(s i k dx/2); exactly real at the Nyquist bin (k dx/2 = -pi/2)
-float2 shift_deriv(double k, double dx, int s, bool nyquist) {
-  const double th = s * k * dx / 2.0;
-  if (nyquist) return f2(-k * std::sin(th), 0.0);
-  return f2(-k * std::sin(th), k * std::cos(th));
-}
-
 double pml_factor(double pos, int n, double seam, const pat_grid& g) {
   if (g.pml_size == 0) return 1.0;
   double dist = std::fmod(std::fabs(pos - seam), (double)n);
@@ -198,6 +189,7 @@ struct pat_plan {
   float* img[7];
   float* dual;
   float* data[6];
+  int fftp;                 // FftPrecision of the propagator kernels
   KernelTimer timer;        // active when timer.ev != nullptr
   std::vector<hipEvent_t> timer_events;
   std::vector<int> timer_ids;
@@ -211,42 +203,46 @@ T* ws_ptr(pat_plan* p, size_t off) { return reinterpret_cast<T*>(p->ws + off); }
 pat_status build_tables(pat_plan* P, const pat_sampling* s) {
   const pat_grid& g = P->g;
   const int NX = g.nx, NY = g.ny, NZ = g.nz, MX = NX / 2, NKX = MX + 1;
-  std::vector<float2> c2;   // complex tables, concatenated
-  std::vector<float> r;     // real tables
+  struct C64 { double re, im; };
+  std::vector<C64> c2;      // complex tables (FP64), concatenated
+  std::vector<double> r;    // sinc argument tables (FP64)
+  std::vector<float> pm;    // PML tables
   std::vector<int> iv;      // index tables
   auto twiddles = [&](int L, int count) {
     size_t o = c2.size();
-    for (int j = 0; j < count; ++j) c2.push_back(f2(std::cos(-2.0 * M_PI * j / L), std::sin(-2.0 * M_PI * j / L)));
+    for (int j = 0; j < count; ++j) c2.push_back({std::cos(-2.0 * M_PI * j / L), std::sin(-2.0 * M_PI * j / L)});
     return o;
   };
   const size_t o_twmx = twiddles(MX, MX), o_twnx = twiddles(NX, MX + 1);
   const size_t o_twy = twiddles(NY, NY), o_twz = twiddles(NZ, NZ);
-  // derivative multipliers and sinc arguments
-  const double hs = g.c0 * g.dt / 2.0;
-  size_t o_mpx = c2.size();
-  for (int kx = 0; kx < NKX; ++kx) c2.push_back(shift_deriv(wavenumber(kx, NX, g.dx), g.dx, +1, 2 * kx == NX));
-  size_t o_mmx = c2.size();
-  for (int kx = 0; kx < NKX; ++kx) c2.push_back(shift_deriv(wavenumber(kx, NX, g.dx), g.dx, -1, 2 * kx == NX));
+  // derivative multipliers i k exp(+-i k dx/2), exactly real at the Nyquist bin
+  auto deriv = [&](int f, int n, int sgn) {
+    const double k = wavenumber(f, n, g.dx);
+    const double th = sgn * k * g.dx / 2.0;
+    return 2 * f == n ? C64{-k * std::sin(th), 0.0} : C64{-k * std::sin(th), k * std::cos(th)};
+  };
+  const size_t o_mpx = c2.size();
+  for (int kx = 0; kx < NKX; ++kx) c2.push_back(deriv(kx, NX, +1));
+  const size_t o_mmx = c2.size();
+  for (int kx = 0; kx < NKX; ++kx) c2.push_back(deriv(kx, NX, -1));
   auto axis_mult = [&](int n, int sgn) {
     size_t o = c2.size();
-    for (int p = 0; p < n; ++p) {
-      const int f = fft_freq(n, p);
-      c2.push_back(shift_deriv(wavenumber(f, n, g.dx), g.dx, sgn, 2 * f == n));
-    }
+    for (int p = 0; p < n; ++p) c2.push_back(deriv(fft_freq(n, p), n, sgn));
     return o;
   };
   const size_t o_mpy = axis_mult(NY, +1), o_mmy = axis_mult(NY, -1);
   const size_t o_mpz = axis_mult(NZ, +1), o_mmz = axis_mult(NZ, -1);
-  size_t o_hx = r.size();
-  for (int kx = 0; kx < NKX; ++kx) r.push_back((float)(hs * wavenumber(kx, NX, g.dx)));
-  size_t o_hy = r.size();
-  for (int p = 0; p < NY; ++p) r.push_back((float)(hs * wavenumber(fft_freq(NY, p), NY, g.dx)));
-  size_t o_hz = r.size();
-  for (int q = 0; q < NZ; ++q) r.push_back((float)(hs * wavenumber(fft_freq(NZ, q), NZ, g.dx)));
+  const double hs = g.c0 * g.dt / 2.0;
+  const size_t o_hx = r.size();
+  for (int kx = 0; kx < NKX; ++kx) r.push_back(hs * wavenumber(kx, NX, g.dx));
+  const size_t o_hy = r.size();
+  for (int p = 0; p < NY; ++p) r.push_back(hs * wavenumber(fft_freq(NY, p), NY, g.dx));
+  const size_t o_hz = r.size();
+  for (int q = 0; q < NZ; ++q) r.push_back(hs * wavenumber(fft_freq(NZ, q), NZ, g.dx));
   // PML factors: staggered (a) at i + 1/2, collocated (b) at i
   auto pml = [&](int n, double seam, double shift) {
-    size_t o = r.size();
-    for (int i = 0; i < n; ++i) r.push_back((float)pml_factor(i + shift, n, seam, g));
+    size_t o = pm.size();
+    for (int i = 0; i < n; ++i) pm.push_back((float)pml_factor(i + shift, n, seam, g));
     return o;
   };
   const double seam_xy = -0.5, seam_z = (double)NZ - g.pml_size - 0.5;
@@ -270,24 +266,45 @@ pat_status build_tables(pat_plan* P, const pat_sampling* s) {
     iv.resize(iv.size() + P->npix, 0);
     for (int q = 0; q < P->npix; ++q) iv[o_invperm + s->perm[q]] = q;
   }
-  const size_t bc2 = align_up(c2.size() * sizeof(float2));
-  const size_t br = align_up(r.size() * sizeof(float));
-  const size_t bi = align_up(std::max<size_t>(iv.size(), 1) * sizeof(int));
-  PAT_TRY_HIP(hipMalloc(&P->tables, bc2 + br + bi));
+  // device images: complex as float2 and double2, real as float and double
+  std::vector<float2> cf(c2.size());
+  std::vector<double2> cd(c2.size());
+  for (size_t i = 0; i < c2.size(); ++i) {
+    cf[i] = make_float2((float)c2[i].re, (float)c2[i].im);
+    cd[i] = make_double2(c2[i].re, c2[i].im);
+  }
+  std::vector<float> rf(r.begin(), r.end());
+  const size_t b_cf = align_up(cf.size() * sizeof(float2)), b_cd = align_up(cd.size() * sizeof(double2));
+  const size_t b_rf = align_up(rf.size() * sizeof(float)), b_rd = align_up(r.size() * sizeof(double));
+  const size_t b_pm = align_up(pm.size() * sizeof(float));
+  const size_t b_iv = align_up(std::max<size_t>(iv.size(), 1) * sizeof(int));
+  PAT_TRY_HIP(hipMalloc(&P->tables, b_cf + b_cd + b_rf + b_rd + b_pm + b_iv));
   char* base = static_cast<char*>(P->tables);
-  PAT_TRY_HIP(hipMemcpy(base, c2.data(), c2.size() * sizeof(float2), hipMemcpyHostToDevice));
-  PAT_TRY_HIP(hipMemcpy(base + bc2, r.data(), r.size() * sizeof(float), hipMemcpyHostToDevice));
-  if (!iv.empty()) PAT_TRY_HIP(hipMemcpy(base + bc2 + br, iv.data(), iv.size() * sizeof(int), hipMemcpyHostToDevice));
-  const float2* dc = reinterpret_cast<const float2*>(base);
-  const float* dr = reinterpret_cast<const float*>(base + bc2);
-  const int* di = reinterpret_cast<const int*>(base + bc2 + br);
+  char* p_cf = base;
+  char* p_cd = p_cf + b_cf;
+  char* p_rf = p_cd + b_cd;
+  char* p_rd = p_rf + b_rf;
+  char* p_pm = p_rd + b_rd;
+  char* p_iv = p_pm + b_pm;
+  PAT_TRY_HIP(hipMemcpy(p_cf, cf.data(), cf.size() * sizeof(float2), hipMemcpyHostToDevice));
+  PAT_TRY_HIP(hipMemcpy(p_cd, cd.data(), cd.size() * sizeof(double2), hipMemcpyHostToDevice));
+  PAT_TRY_HIP(hipMemcpy(p_rf, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice));
+  PAT_TRY_HIP(hipMemcpy(p_rd, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
+  PAT_TRY_HIP(hipMemcpy(p_pm, pm.data(), pm.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (!iv.empty()) PAT_TRY_HIP(hipMemcpy(p_iv, iv.data(), iv.size() * sizeof(int), hipMemcpyHostToDevice));
+  auto fill = [&](auto& T, auto* dc, auto* dr) {
+    T.tw_mx = dc + o_twmx; T.tw_nx = dc + o_twnx; T.tw_y = dc + o_twy; T.tw_z = dc + o_twz;
+    T.mpx = dc + o_mpx; T.mmx = dc + o_mmx; T.mpy = dc + o_mpy; T.mmy = dc + o_mmy;
+    T.mpz = dc + o_mpz; T.mmz = dc + o_mmz;
+    T.hx = dr + o_hx; T.hy = dr + o_hy; T.hz = dr + o_hz;
+  };
   WaveTables& t = P->tabs;
-  t.tw_mx = dc + o_twmx; t.tw_nx = dc + o_twnx; t.tw_y = dc + o_twy; t.tw_z = dc + o_twz;
-  t.mpx = dc + o_mpx; t.mmx = dc + o_mmx; t.mpy = dc + o_mpy; t.mmy = dc + o_mmy;
-  t.mpz = dc + o_mpz; t.mmz = dc + o_mmz;
-  t.hx = dr + o_hx; t.hy = dr + o_hy; t.hz = dr + o_hz;
-  t.ax = dr + o_ax; t.ay = dr + o_ay; t.az = dr + o_az;
-  t.bx = dr + o_bx; t.by = dr + o_by; t.bz = dr + o_bz;
+  fill(t.f, reinterpret_cast<const float2*>(p_cf), reinterpret_cast<const float*>(p_rf));
+  fill(t.d, reinterpret_cast<const double2*>(p_cd), reinterpret_cast<const double*>(p_rd));
+  const float* dp = reinterpret_cast<const float*>(p_pm);
+  t.ax = dp + o_ax; t.ay = dp + o_ay; t.az = dp + o_az;
+  t.bx = dp + o_bx; t.by = dp + o_by; t.bz = dp + o_bz;
+  const int* di = reinterpret_cast<const int*>(p_iv);
   P->idx = s->kind != PAT_SAMPLE_FULL ? di + o_idx : nullptr;
   P->inv = s->kind == PAT_SAMPLE_POINTS ? di + o_inv : nullptr;
   P->perm = s->kind == PAT_SAMPLE_HADAMARD ? di + o_perm : nullptr;
@@ -316,7 +333,7 @@ long data_n(const pat_plan* P) { return (long)P->g.nt * P->mc; }
 // ---- operator pieces used by the entry points and the solver ----------------
 pat_status op_forward(pat_plan* P, const float* p0, float* f) {
   float* planes = P->kind == PAT_SAMPLE_FULL ? f : P->planes;
-  PAT_TRY_HIP(P->impl->forward(P->tabs, P->sc, P->wb, p0, planes, P->g.nt, P->stream,
+  PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, planes, P->g.nt, P->stream,
                                P->timer.ev ? &P->timer : nullptr));
   if (P->kind == PAT_SAMPLE_POINTS)
     PAT_TRY_HIP(launch_rsp_gather(planes, P->idx, f, P->npix, P->mc, P->g.nt, P->stream));
@@ -334,7 +351,7 @@ pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
     PAT_TRY_HIP(launch_shd_adjoint(f, P->invperm, P->idx, P->planes, P->npix, P->mc, P->g.nt, P->stream));
     planes = P->planes;
   }
-  PAT_TRY_HIP(P->impl->adjoint(P->tabs, P->sc, P->wb, planes, p, P->g.nt, P->stream,
+  PAT_TRY_HIP(P->impl->adjoint[P->fftp](P->tabs, P->sc, P->wb, planes, p, P->g.nt, P->stream,
                                P->timer.ev ? &P->timer : nullptr));
   return PAT_OK;
 }
@@ -433,6 +450,7 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
   P->npix = grid->nx * grid->ny;
   P->stream = static_cast<hipStream_t>(stream);
   P->impl = find_wave_impl(grid->nx, grid->ny, grid->nz);
+  P->fftp = FFT_FP64;
   if (hipGetDevice(&P->device) != hipSuccess) {
     delete P;
     return set_error(PAT_ERR_HIP, "hipGetDevice failed (no GPU?)");
@@ -476,6 +494,13 @@ pat_status pat_plan_destroy(pat_plan* plan) {
 pat_status pat_plan_set_stream(pat_plan* plan, void* stream) {
   PAT_TRY(check_plan(plan));
   plan->stream = static_cast<hipStream_t>(stream);
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_fft_precision(pat_plan* plan, int32_t bits) {
+  PAT_TRY(check_plan(plan));
+  if (bits != 32 && bits != 64) return set_error(PAT_ERR_INVALID, "pat_plan_set_fft_precision: bits must be 32 or 64");
+  plan->fftp = bits == 64 ? FFT_FP64 : FFT_FP32;
   return PAT_OK;
 }
 

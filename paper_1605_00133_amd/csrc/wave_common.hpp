@@ -12,20 +12,27 @@ namespace pat {
 //   kx in [0, nx/2] natural order (half spectrum of the real x transform),
 //   ky_pos = position of ky after the forward y transform (digit-reversed),
 //   and in the z-pencil kernels kz_pos likewise for z.
+// The spectral tables exist in both arithmetic types (float2 / double2).
+template <typename V, typename S>
+struct SpecTables {
+  const V* tw_mx;   // exp(-2 pi i j / (nx/2)), j < nx/2
+  const V* tw_nx;   // exp(-2 pi i k / nx),     k <= nx/2
+  const V* tw_y;    // exp(-2 pi i j / ny),     j < ny
+  const V* tw_z;    // exp(-2 pi i j / nz),     j < nz
+  const V* mpx;     // i kx exp(+i kx dx/2), indexed by kx
+  const V* mmx;     // i kx exp(-i kx dx/2)
+  const V* mpy;     // same for y, indexed by ky_pos
+  const V* mmy;
+  const V* mpz;     // same for z, indexed by kz_pos
+  const V* mmz;
+  const S* hx;      // (c0 dt / 2) kx   (argument scale of the k-space sinc)
+  const S* hy;      // by ky_pos
+  const S* hz;      // by kz_pos
+};
+
 struct WaveTables {
-  const float2* tw_mx;   // exp(-2 pi i j / (nx/2)), j < nx/2
-  const float2* tw_nx;   // exp(-2 pi i k / nx),     k <= nx/2
-  const float2* tw_y;    // exp(-2 pi i j / ny),     j < ny
-  const float2* tw_z;    // exp(-2 pi i j / nz),     j < nz
-  const float2* mpx;     // i kx exp(+i kx dx/2), indexed by kx
-  const float2* mmx;     // i kx exp(-i kx dx/2)
-  const float2* mpy;     // same for y, indexed by ky_pos
-  const float2* mmy;
-  const float2* mpz;     // same for z, indexed by kz_pos
-  const float2* mmz;
-  const float* hx;       // (c0 dt / 2) kx   (argument scale of the k-space sinc)
-  const float* hy;       // by ky_pos
-  const float* hz;       // by kz_pos
+  SpecTables<float2, float> f;
+  SpecTables<double2, double> d;
   const float* ax;       // PML factor at staggered points i + 1/2
   const float* ay;
   const float* az;
@@ -77,10 +84,14 @@ using WaveLaunchFwd = hipError_t (*)(const WaveTables&, const WaveScalars&, cons
 using WaveLaunchAdj = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
                                      const float* planes, float* p, int nt, hipStream_t, KernelTimer*);
 
+// FFT arithmetic of the propagator kernels: FP32, or FP64 in registers and
+// LDS with FP32 storage in HBM.
+enum FftPrecision { FFT_FP32 = 0, FFT_FP64 = 1 };
+
 struct WaveImpl {
   int nx, ny, nz;
-  WaveLaunchFwd forward;
-  WaveLaunchAdj adjoint;
+  WaveLaunchFwd forward[2];   // indexed by FftPrecision
+  WaveLaunchAdj adjoint[2];
 };
 
 // Returns nullptr when the size is not built.

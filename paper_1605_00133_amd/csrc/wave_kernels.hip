@@ -15,9 +15,11 @@
 //     update of the state fields;
 //   pencil kernels (one workgroup per 16 ky columns of one kx, all z): z
 //     transform in LDS, the k-space multipliers, inverse z transform.
-// Slab spectra live in HBM as [z][kx][ky_pos] (kx = 0..nx/2 natural, ky in
-// digit-reversed position order), so pencil tiles read 128-byte rows and no
-// kernel ever permutes data.
+// Slab spectra live in HBM as float2 [z][kx][ky_pos] (kx = 0..nx/2 natural, ky
+// in digit-reversed position order), so pencil tiles read 128-byte rows and no
+// kernel ever permutes data. The state fields are float in HBM and updated in
+// FP32; the transforms run in the arithmetic type V (float2, or double2 for
+// FP64 butterflies with a single FP32 rounding per pass).
 //
 // Forward step = pencil(grad: 1 in, 2 out) -> slab(u: per component) ->
 // pencil(div: per component) -> slab(rho, p, sensor plane, R2C of p).
@@ -30,8 +32,11 @@
 
 namespace pat {
 
-constexpr int kThreadsXY = 256;
 constexpr int kThreadsZ = 128;
+
+// threads per slab workgroup (8 waves): FP32 slabs of 128^2 take 66.5 KB of LDS
+// (two workgroups per CU), FP64 slabs 133 KB (one per CU, up to 256 VGPRs).
+template <typename V> struct SlabThreads { static constexpr int value = 512; };
 
 template <int NX, int NY, int NZ>
 struct Dims {
@@ -42,168 +47,276 @@ struct Dims {
   static constexpr int SLAB_P = NY * MX;     // float2 pairs per real slab
   static constexpr int TY = NY >= 16 ? 16 : NY;
   static constexpr int NTILE = NKX * (NY / TY);
-  static constexpr int EPT = (SLAB_P + kThreadsXY - 1) / kThreadsXY;
+  static constexpr int ZIT = (NZ * TY + kThreadsZ - 1) / kThreadsZ;   // tile elements per z thread
+  // rows per chunk of the real-FFT pre/post-processing (bounds its registers)
+  static constexpr int NP = MX / 2 + 1;
+  static constexpr int RC0 = 1024 / NP >= NY ? NY : (1024 / NP >= 64 ? 64 : 1024 / NP >= 32 ? 32 : 1024 / NP >= 16 ? 16 : 8);
+  static constexpr int RC = RC0 > NY ? NY : RC0;
 };
+
+template <typename V> struct TabSel;
+template <> struct TabSel<float2> {
+  static __device__ __forceinline__ const SpecTables<float2, float>& get(const WaveTables& t) { return t.f; }
+};
+template <> struct TabSel<double2> {
+  static __device__ __forceinline__ const SpecTables<double2, double>& get(const WaveTables& t) { return t.d; }
+};
+
+// sinc(sqrt(s)) = sin(h)/h at h^2 = s
+__device__ __forceinline__ float sinc_of_sq(float s) {
+  const float h = sqrtf(s);
+  return h > 0.f ? sinf(h) / h : 1.f;
+}
+__device__ __forceinline__ double sinc_of_sq(double s) {
+  if (s < 2.5) {
+    // Taylor series sum_k (-s)^k / (2k+1)!, truncated after k = 12 (< 4e-21 at s = 2.5)
+    double r = 1.0 / 15511210043330985984000000.0;
+    r = r * -s + 1.0 / 25852016738884976640000.0;
+    r = r * -s + 1.0 / 51090942171709440000.0;
+    r = r * -s + 1.0 / 121645100408832000.0;
+    r = r * -s + 1.0 / 355687428096000.0;
+    r = r * -s + 1.0 / 1307674368000.0;
+    r = r * -s + 1.0 / 6227020800.0;
+    r = r * -s + 1.0 / 39916800.0;
+    r = r * -s + 1.0 / 362880.0;
+    r = r * -s + 1.0 / 5040.0;
+    r = r * -s + 1.0 / 120.0;
+    r = r * -s + 1.0 / 6.0;
+    return r * -s + 1.0;
+  }
+  const double h = sqrt(s);
+  return sin(h) / h;
+}
 
 // ---- slab transforms -------------------------------------------------------
 
 // R2C post-processing of rows already transformed by a forward MX-point FFT:
 // row y holds Z[k] (Z = FFT of x[2n] + i x[2n+1]) at digit-reversed positions;
 // on exit it holds X[k], k = 0..MX, in natural order (X = real FFT of x).
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void r2c_post(float2* S, const float2* __restrict__ tw_nx, int tid) {
+// Rows are processed in chunks of RC: read all pairs of the chunk, barrier, write.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void r2c_post(V* S, const V* __restrict__ tw_nx, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int MX = D::MX, NP = MX / 2 + 1, TOTAL = NY * NP;
-  constexpr int IT = (TOTAL + kThreadsXY - 1) / kThreadsXY;
-  float2 o1[IT], o2[IT];
+  constexpr int NT = SlabThreads<V>::value;
+  using Sc = typename ScalarOf<V>::T;
+  constexpr int MX = D::MX, NP = D::NP, TOTAL = D::RC * NP;
+  constexpr int IT = (TOTAL + NT - 1) / NT;
+  for (int r0 = 0; r0 < NY; r0 += D::RC) {
+    V o1[IT], o2[IT];
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * kThreadsXY;
-    if (w < TOTAL) {
-      const int y = w / NP, k = w % NP;
-      const float2* row = S + y * D::PITCH;
-      if (k == 0) {
-        const float2 z0 = row[0];
-        o1[i] = make_float2(z0.x + z0.y, 0.f);
-        o2[i] = make_float2(z0.x - z0.y, 0.f);
-      } else {
-        const float2 A = row[fft_pos(MX, k)];
-        const float2 B = cconj(row[fft_pos(MX, MX - k)]);
-        const float2 E = cscale(cadd(A, B), 0.5f);
-        const float2 Dd = csub(A, B);
-        const float2 O = make_float2(0.5f * Dd.y, -0.5f * Dd.x);   // (A - B) / (2i)
-        const float2 WO = cmul(tw_nx[k], O);
-        o1[i] = cadd(E, WO);
-        o2[i] = cconj(csub(E, WO));
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < TOTAL) {
+        const int y = r0 + w / NP, k = w % NP;
+        const V* row = S + y * D::PITCH;
+        if (k == 0) {
+          const V z0 = row[0];
+          o1[i] = mkc<V>(z0.x + z0.y, (Sc)0);
+          o2[i] = mkc<V>(z0.x - z0.y, (Sc)0);
+        } else {
+          const V A = row[fft_pos(MX, k)];
+          const V B = cconj(row[fft_pos(MX, MX - k)]);
+          const V E = cscale(cadd(A, B), (Sc)0.5);
+          const V Dd = csub(A, B);
+          const V O = mkc<V>((Sc)0.5 * Dd.y, (Sc)-0.5 * Dd.x);   // (A - B) / (2i)
+          const V WO = cmul(tw_nx[k], O);
+          o1[i] = cadd(E, WO);
+          o2[i] = cconj(csub(E, WO));
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * kThreadsXY;
-    if (w < TOTAL) {
-      const int y = w / NP, k = w % NP;
-      float2* row = S + y * D::PITCH;
-      row[k] = o1[i];
-      row[MX - k] = o2[i];   // k == 0 writes X[MX]; k == MX/2 rewrites the same value
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < TOTAL) {
+        const int y = r0 + w / NP, k = w % NP;
+        V* row = S + y * D::PITCH;
+        row[k] = o1[i];
+        row[MX - k] = o2[i];   // k == 0 writes X[MX]; k == MX/2 rewrites the same value
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // C2R pre-processing: row y holds X[k], k = 0..MX natural; on exit it holds
 // Z'[k] = (X[k] + conj X[MX-k]) + i exp(+2 pi i k/NX) (X[k] - conj X[MX-k]) at
 // digit-reversed positions, so that an inverse MX-point FFT yields
 // x[2n] + i x[2n+1] (unnormalised real inverse transform).
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void c2r_pre(float2* S, const float2* __restrict__ tw_nx, int tid) {
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void c2r_pre(V* S, const V* __restrict__ tw_nx, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int MX = D::MX, NP = MX / 2 + 1, TOTAL = NY * NP;
-  constexpr int IT = (TOTAL + kThreadsXY - 1) / kThreadsXY;
-  float2 o1[IT], o2[IT];
+  constexpr int NT = SlabThreads<V>::value;
+  constexpr int MX = D::MX, NP = D::NP, TOTAL = D::RC * NP;
+  constexpr int IT = (TOTAL + NT - 1) / NT;
+  for (int r0 = 0; r0 < NY; r0 += D::RC) {
+    V o1[IT], o2[IT];
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * kThreadsXY;
-    if (w < TOTAL) {
-      const int y = w / NP, k = w % NP;
-      const float2* row = S + y * D::PITCH;
-      const float2 Xk = row[k], Xm = row[MX - k];
-      {
-        const float2 s = cadd(Xk, cconj(Xm)), d = csub(Xk, cconj(Xm));
-        const float2 wd = cmulconj(d, tw_nx[k]);
-        o1[i] = make_float2(s.x - wd.y, s.y + wd.x);
-      }
-      {
-        const float2 s = cadd(Xm, cconj(Xk)), d = csub(Xm, cconj(Xk));
-        const float2 wd = cmulconj(d, tw_nx[MX - k]);
-        o2[i] = make_float2(s.x - wd.y, s.y + wd.x);
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < TOTAL) {
+        const int y = r0 + w / NP, k = w % NP;
+        const V* row = S + y * D::PITCH;
+        const V Xk = row[k], Xm = row[MX - k];
+        {
+          const V s = cadd(Xk, cconj(Xm)), d = csub(Xk, cconj(Xm));
+          const V wd = cmulconj(d, tw_nx[k]);
+          o1[i] = mkc<V>(s.x - wd.y, s.y + wd.x);
+        }
+        {
+          const V s = cadd(Xm, cconj(Xk)), d = csub(Xm, cconj(Xk));
+          const V wd = cmulconj(d, tw_nx[MX - k]);
+          o2[i] = mkc<V>(s.x - wd.y, s.y + wd.x);
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * kThreadsXY;
-    if (w < TOTAL) {
-      const int y = w / NP, k = w % NP;
-      float2* row = S + y * D::PITCH;
-      row[fft_pos(MX, k)] = o1[i];
-      if (k != 0 && 2 * k != MX) row[fft_pos(MX, MX - k)] = o2[i];
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < TOTAL) {
+        const int y = r0 + w / NP, k = w % NP;
+        V* row = S + y * D::PITCH;
+        row[fft_pos(MX, k)] = o1[i];
+        if (k != 0 && 2 * k != MX) row[fft_pos(MX, MX - k)] = o2[i];
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Real slab (packed pairs at S[y*PITCH + n]) -> slab spectrum (kx natural,
 // ky digit-reversed) in place. Caller syncs before.
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void slab_r2c(float2* S, const WaveTables& t, int tid) {
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void slab_r2c(V* S, const WaveTables& t, int tid) {
   using D = Dims<NX, NY, NZ>;
-  fft_forward<D::MX, false>(S, NY, D::PITCH, 1, t.tw_mx, tid, kThreadsXY);
-  r2c_post<NX, NY, NZ>(S, t.tw_nx, tid);
-  fft_forward<NY, true>(S, D::NKX, 1, D::PITCH, t.tw_y, tid, kThreadsXY);
+  constexpr int NT = SlabThreads<V>::value;
+  const auto& T = TabSel<V>::get(t);
+  fft_forward<D::MX, false>(S, NY, D::PITCH, 1, T.tw_mx, tid, NT);
+  r2c_post<NX, NY, NZ>(S, T.tw_nx, tid);
+  fft_forward<NY, true>(S, D::NKX, 1, D::PITCH, T.tw_y, tid, NT);
 }
 
 // Slab spectrum -> real slab (packed pairs), unnormalised. Caller syncs before.
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void slab_c2r(float2* S, const WaveTables& t, int tid) {
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void slab_c2r(V* S, const WaveTables& t, int tid) {
   using D = Dims<NX, NY, NZ>;
-  fft_inverse<NY, true>(S, D::NKX, 1, D::PITCH, t.tw_y, tid, kThreadsXY);
-  c2r_pre<NX, NY, NZ>(S, t.tw_nx, tid);
-  fft_inverse<D::MX, false>(S, NY, D::PITCH, 1, t.tw_mx, tid, kThreadsXY);
+  constexpr int NT = SlabThreads<V>::value;
+  const auto& T = TabSel<V>::get(t);
+  fft_inverse<NY, true>(S, D::NKX, 1, D::PITCH, T.tw_y, tid, NT);
+  c2r_pre<NX, NY, NZ>(S, T.tw_nx, tid);
+  fft_inverse<D::MX, false>(S, NY, D::PITCH, 1, T.tw_mx, tid, NT);
 }
 
 // Global slab spectrum [kx][ky_pos] -> LDS [ky_pos][kx], times mult (0: none,
 // 1: per-kx table, 2: per-ky_pos table).
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void load_spec(float2* S, const float2* __restrict__ g, int mode,
-                                          const float2* __restrict__ mult, int tid) {
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void load_spec(V* S, const float2* __restrict__ g, int mode,
+                                          const V* __restrict__ mult, int tid) {
   using D = Dims<NX, NY, NZ>;
-  for (int e = tid; e < D::SLAB_C; e += kThreadsXY) {
-    const int kx = e / NY, p = e % NY;
-    float2 v = g[e];
-    if (mode == 1) v = cmul(v, mult[kx]);
-    else if (mode == 2) v = cmul(v, mult[p]);
-    S[p * D::PITCH + kx] = v;
+  constexpr int NT = SlabThreads<V>::value;
+  constexpr int IT = (D::SLAB_C + NT - 1) / NT;
+  float2 r[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {     // all global loads in flight before any LDS write
+    const int e = tid + i * NT;
+    if (e < D::SLAB_C) r[i] = g[e];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    if (e < D::SLAB_C) {
+      const int kx = e / NY, p = e % NY;
+      V v = widen<V>(r[i]);
+      if (mode == 1) v = cmul(v, mult[kx]);
+      else if (mode == 2) v = cmul(v, mult[p]);
+      S[p * D::PITCH + kx] = v;
+    }
   }
 }
 
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void store_spec(const float2* S, float2* __restrict__ g, int tid) {
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void store_spec(const V* S, float2* __restrict__ g, int tid) {
   using D = Dims<NX, NY, NZ>;
-  for (int e = tid; e < D::SLAB_C; e += kThreadsXY) {
-    const int kx = e / NY, p = e % NY;
-    g[e] = S[p * D::PITCH + kx];
+  constexpr int NT = SlabThreads<V>::value;
+  constexpr int IT = (D::SLAB_C + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    if (e < D::SLAB_C) {
+      const int kx = e / NY, p = e % NY;
+      g[e] = narrow(S[p * D::PITCH + kx]);
+    }
+  }
+}
+
+// Batched read of a z-pencil tile (fixed kx, TY consecutive ky_pos, all z) into
+// LDS columns [col0, col0 + TY) of a row pitch W.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void load_tile(V* T, int W, int col0, const float2* __restrict__ H, int kx, int p0,
+                                          int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int TY = D::TY;
+  float2 r[D::ZIT];
+#pragma unroll
+  for (int i = 0; i < D::ZIT; ++i) {
+    const int e = tid + i * kThreadsZ;
+    if (e < NZ * TY) r[i] = H[((size_t)(e / TY) * D::NKX + kx) * NY + p0 + e % TY];
+  }
+#pragma unroll
+  for (int i = 0; i < D::ZIT; ++i) {
+    const int e = tid + i * kThreadsZ;
+    if (e < NZ * TY) T[(e / TY) * W + col0 + e % TY] = widen<V>(r[i]);
+  }
+}
+
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void store_tile(const V* T, int W, int col0, float2* __restrict__ H, int kx, int p0,
+                                           int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int TY = D::TY;
+#pragma unroll
+  for (int i = 0; i < D::ZIT; ++i) {
+    const int e = tid + i * kThreadsZ;
+    if (e < NZ * TY) H[((size_t)(e / TY) * D::NKX + kx) * NY + p0 + e % TY] = narrow(T[(e / TY) * W + col0 + e % TY]);
   }
 }
 
 // blockIdx -> (slab z, component xi) so the three components of one slab run on
 // the same XCD (block ids congruent mod 8), sharing that XCD's L2.
-template <int NZ>
 __device__ __forceinline__ void slab_field_of_block(int b, int& z, int& xi) {
   const int grp = b / 24, r = b % 24;
   xi = r / 8;
   z = grp * 8 + (r % 8);
 }
 
+// k-space correction sinc(c0 dt |k|/2) / N at (kx, ky_pos, kz_pos)
+template <typename V, typename T>
+__device__ __forceinline__ typename ScalarOf<V>::T kappa_at(const T& tab, int kx, int p, int q,
+                                                            typename ScalarOf<V>::T inv_ntot) {
+  const auto hx = tab.hx[kx], hy = tab.hy[p], hz = tab.hz[q];
+  return sinc_of_sq(hx * hx + hy * hy + hz * hz) * inv_ntot;
+}
+
 // ---- forward kernels ---------------------------------------------------------
 
 // rho_xi = p0 / (3 c0^2); plane 0 = p0[z = 0]; spec0 = slab R2C of p0.
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_fwd_init(const float* __restrict__ p0, WaveBuffers B,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_init(const float* __restrict__ p0, WaveBuffers B,
                                                          float* __restrict__ plane0, WaveTables t,
                                                          WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t off = (size_t)z * D::SLAB_P;
   const float2* src = reinterpret_cast<const float2*>(p0) + off;
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+  for (int e = tid; e < D::SLAB_P; e += NT) {
     const int y = e / D::MX, n = e % D::MX;
     const float2 v = src[e];
-    S[y * D::PITCH + n] = v;
-    const float2 r = cscale(v, sc.inv_3c2);
+    S[y * D::PITCH + n] = widen<V>(v);
+    const float2 r = make_float2(v.x * sc.inv_3c2, v.y * sc.inv_3c2);
 #pragma unroll
     for (int xi = 0; xi < 3; ++xi) reinterpret_cast<float2*>(B.rho[xi])[off + e] = r;
     if (z == 0) reinterpret_cast<float2*>(plane0)[e] = v;
@@ -217,109 +330,107 @@ __global__ __launch_bounds__(kThreadsXY) void k_fwd_init(const float* __restrict
 // Q = IFFT_z[kappa FFT_z(in)] / N and Gz = IFFT_z[kappa i kz e^{i kz dx/2} FFT_z(in)] / N.
 // The x and y derivative factors are applied later in the slab kernel (they
 // depend only on kx or ky_pos), so one input yields two outputs instead of three.
-template <int NX, int NY, int NZ>
+template <int NX, int NY, int NZ, typename V>
 __global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, float2* __restrict__ Gz,
                                                      WaveTables t, float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
+  using Sc = typename ScalarOf<V>::T;
   constexpr int TY = D::TY, W = 2 * TY;
-  __shared__ float2 T[NZ * W];
+  __shared__ V T[NZ * W];
+  const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-    const int z = e / TY, j = e % TY;
-    T[z * W + j] = P[((size_t)z * D::NKX + kx) * NY + p0 + j];
-  }
+  load_tile<NX, NY, NZ>(T, W, 0, P, kx, p0, tid);
   __syncthreads();
-  fft_forward<NZ, true>(T, TY, 1, W, t.tw_z, tid, kThreadsZ);
-  const float hx = t.hx[kx];
+  fft_forward<NZ, true>(T, TY, 1, W, tab.tw_z, tid, kThreadsZ);
   for (int e = tid; e < NZ * TY; e += kThreadsZ) {
     const int q = e / TY, j = e % TY;
-    const float hy = t.hy[p0 + j], hz = t.hz[q];
-    const float h = sqrtf(hx * hx + hy * hy + hz * hz);
-    const float kap = (h > 0.f ? sinf(h) / h : 1.f) * inv_ntot;
-    const float2 v = cscale(T[q * W + j], kap);
+    const Sc kap = kappa_at<V>(tab, kx, p0 + j, q, (Sc)inv_ntot);
+    const V v = cscale(T[q * W + j], kap);
     T[q * W + j] = v;
-    T[q * W + TY + j] = cmul(v, t.mpz[q]);
+    T[q * W + TY + j] = cmul(v, tab.mpz[q]);
   }
   __syncthreads();
-  fft_inverse<NZ, true>(T, W, 1, W, t.tw_z, tid, kThreadsZ);
-  for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-    const int z = e / TY, j = e % TY;
-    const size_t gi = ((size_t)z * D::NKX + kx) * NY + p0 + j;
-    P[gi] = T[z * W + j];
-    Gz[gi] = T[z * W + TY + j];
-  }
+  fft_inverse<NZ, true>(T, W, 1, W, tab.tw_z, tid, kThreadsZ);
+  store_tile<NX, NY, NZ>(T, W, 0, P, kx, p0, tid);
+  store_tile<NX, NY, NZ>(T, W, TY, Gz, kx, p0, tid);
 }
 
 // Pencil pass applying kappa/N times i k_xi exp(s i k_xi dx/2) (PLUS: s = +1,
 // else -1) to component xi = blockIdx.y, in place.
-template <int NX, int NY, int NZ, bool PLUS>
+template <int NX, int NY, int NZ, typename V, bool PLUS>
 __global__ __launch_bounds__(kThreadsZ) void k_zmul(float2* H0, float2* H1, float2* H2, WaveTables t,
                                                     float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
+  using Sc = typename ScalarOf<V>::T;
   constexpr int TY = D::TY;
-  __shared__ float2 T[NZ * TY];
+  __shared__ V T[NZ * TY];
+  const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x, xi = blockIdx.y;
   float2* H = xi == 0 ? H0 : (xi == 1 ? H1 : H2);
   const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-    const int z = e / TY, j = e % TY;
-    T[e] = H[((size_t)z * D::NKX + kx) * NY + p0 + j];
-  }
+  load_tile<NX, NY, NZ>(T, TY, 0, H, kx, p0, tid);
   __syncthreads();
-  fft_forward<NZ, true>(T, TY, 1, TY, t.tw_z, tid, kThreadsZ);
-  const float hx = t.hx[kx];
-  const float2* mx = PLUS ? t.mpx : t.mmx;
-  const float2* my = PLUS ? t.mpy : t.mmy;
-  const float2* mz = PLUS ? t.mpz : t.mmz;
+  fft_forward<NZ, true>(T, TY, 1, TY, tab.tw_z, tid, kThreadsZ);
+  const V* mx = PLUS ? tab.mpx : tab.mmx;
+  const V* my = PLUS ? tab.mpy : tab.mmy;
+  const V* mz = PLUS ? tab.mpz : tab.mmz;
   for (int e = tid; e < NZ * TY; e += kThreadsZ) {
     const int q = e / TY, j = e % TY;
-    const float hy = t.hy[p0 + j], hz = t.hz[q];
-    const float h = sqrtf(hx * hx + hy * hy + hz * hz);
-    const float kap = (h > 0.f ? sinf(h) / h : 1.f) * inv_ntot;
-    const float2 m = xi == 0 ? mx[kx] : (xi == 1 ? my[p0 + j] : mz[q]);
+    const Sc kap = kappa_at<V>(tab, kx, p0 + j, q, (Sc)inv_ntot);
+    const V m = xi == 0 ? mx[kx] : (xi == 1 ? my[p0 + j] : mz[q]);
     T[e] = cmul(cscale(T[e], kap), m);
   }
   __syncthreads();
-  fft_inverse<NZ, true>(T, TY, 1, TY, t.tw_z, tid, kThreadsZ);
-  for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-    const int z = e / TY, j = e % TY;
-    H[((size_t)z * D::NKX + kx) * NY + p0 + j] = T[e];
-  }
+  fft_inverse<NZ, true>(T, TY, 1, TY, tab.tw_z, tid, kThreadsZ);
+  store_tile<NX, NY, NZ>(T, TY, 0, H, kx, p0, tid);
 }
 
 // Velocity update of component xi for slab z, then R2C of the new u_xi.
 // Q, Gz: outputs of k_zgrad; U0, U1, U2: spectra of the new u components
 // (U2 aliases Gz: only this block reads Gz[z] and it does so before writing).
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_fwd_u(const float2* __restrict__ Q, const float2* Gz,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_u(const float2* __restrict__ Q, const float2* Gz,
                                                       float2* U0, float2* U1, float2* U2, WaveBuffers B,
                                                       WaveTables t, WaveScalars sc, int init) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
+  const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   int z, xi;
-  slab_field_of_block<NZ>(blockIdx.x, z, xi);
+  slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
-  if (xi == 0) load_spec<NX, NY, NZ>(S, Q + cz, 1, t.mpx, tid);
-  else if (xi == 1) load_spec<NX, NY, NZ>(S, Q + cz, 2, t.mpy, tid);
-  else load_spec<NX, NY, NZ>(S, Gz + cz, 0, nullptr, tid);
+  if (xi == 0) load_spec<NX, NY, NZ>(S, Q + cz, 1, tab.mpx, tid);
+  else if (xi == 1) load_spec<NX, NY, NZ>(S, Q + cz, 2, tab.mpy, tid);
+  else load_spec<NX, NY, NZ>(S, Gz + cz, 0, (const V*)nullptr, tid);
+  // prefetch the velocity component: its loads overlap the transform
+  float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
+  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
+  float2 uo[EPT];
+  if (!init) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+      if (tid + i * NT < D::SLAB_P) uo[i] = u[tid + i * NT];
+  }
   __syncthreads();
   slab_c2r<NX, NY, NZ>(S, t, tid);
-  float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
   const float azz = t.az[z];
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (e >= D::SLAB_P) break;
     const int y = e / D::MX, n = e % D::MX;
-    const float2 g = S[y * D::PITCH + n];
+    const float2 g = narrow(S[y * D::PITCH + n]);
     float a0, a1;
     if (xi == 0) { a0 = t.ax[2 * n]; a1 = t.ax[2 * n + 1]; }
     else if (xi == 1) { a0 = a1 = t.ay[y]; }
     else { a0 = a1 = azz; }
-    const float2 uo = init ? cscale(g, sc.half_dt_over_rho0) : u[e];
-    const float2 un = make_float2(a0 * (a0 * uo.x - sc.dt_over_rho0 * g.x),
-                                  a1 * (a1 * uo.y - sc.dt_over_rho0 * g.y));
+    const float2 o = init ? make_float2(g.x * sc.half_dt_over_rho0, g.y * sc.half_dt_over_rho0) : uo[i];
+    const float2 un = make_float2(a0 * (a0 * o.x - sc.dt_over_rho0 * g.x),
+                                  a1 * (a1 * o.y - sc.dt_over_rho0 * g.y));
     u[e] = un;
-    S[y * D::PITCH + n] = un;
+    S[y * D::PITCH + n] = widen<V>(un);
   }
   __syncthreads();
   slab_r2c<NX, NY, NZ>(S, t, tid);
@@ -329,51 +440,57 @@ __global__ __launch_bounds__(kThreadsXY) void k_fwd_u(const float2* __restrict__
 
 // Density update of all three components of slab z, p = c0^2 sum rho, sensor
 // plane, and R2C of p into Pout.
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_fwd_rho(const float2* __restrict__ H0,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_rho(const float2* __restrict__ H0,
                                                         const float2* __restrict__ H1,
                                                         const float2* __restrict__ H2, WaveBuffers B,
                                                         float2* __restrict__ Pout, float* __restrict__ plane,
                                                         WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  float2 pacc[D::EPT];
+  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
+  float2 pacc[EPT];
 #pragma unroll
-  for (int i = 0; i < D::EPT; ++i) pacc[i] = make_float2(0.f, 0.f);
+  for (int i = 0; i < EPT; ++i) pacc[i] = make_float2(0.f, 0.f);
   for (int xi = 0; xi < 3; ++xi) {
     const float2* H = xi == 0 ? H0 : (xi == 1 ? H1 : H2);
-    load_spec<NX, NY, NZ>(S, H + cz, 0, nullptr, tid);
+    load_spec<NX, NY, NZ>(S, H + cz, 0, (const V*)nullptr, tid);
+    float2* r = reinterpret_cast<float2*>(B.rho[xi]) + rz;
     __syncthreads();
     slab_c2r<NX, NY, NZ>(S, t, tid);
-    float2* r = reinterpret_cast<float2*>(B.rho[xi]) + rz;
+    float2 rold[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+      if (tid + i * NT < D::SLAB_P) rold[i] = r[tid + i * NT];
     const float bzz = t.bz[z];
 #pragma unroll
-    for (int i = 0; i < D::EPT; ++i) {
-      const int e = tid + i * kThreadsXY;
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
       if (e < D::SLAB_P) {
         const int y = e / D::MX, n = e % D::MX;
-        const float2 h = S[y * D::PITCH + n];
+        const float2 h = narrow(S[y * D::PITCH + n]);
         float b0, b1;
         if (xi == 0) { b0 = t.bx[2 * n]; b1 = t.bx[2 * n + 1]; }
         else if (xi == 1) { b0 = b1 = t.by[y]; }
         else { b0 = b1 = bzz; }
-        const float2 ro = r[e];
+        const float2 ro = rold[i];
         const float2 rn = make_float2(b0 * (b0 * ro.x - sc.dt_rho0 * h.x), b1 * (b1 * ro.y - sc.dt_rho0 * h.y));
         r[e] = rn;
-        pacc[i] = cadd(pacc[i], rn);
+        pacc[i] = make_float2(pacc[i].x + rn.x, pacc[i].y + rn.y);
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < D::EPT; ++i) {
-    const int e = tid + i * kThreadsXY;
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
     if (e < D::SLAB_P) {
       const int y = e / D::MX, n = e % D::MX;
-      const float2 p = cscale(pacc[i], sc.c2);
-      S[y * D::PITCH + n] = p;
+      const float2 p = make_float2(pacc[i].x * sc.c2, pacc[i].y * sc.c2);
+      S[y * D::PITCH + n] = widen<V>(p);
       if (z == 0) reinterpret_cast<float2*>(plane)[e] = p;
     }
   }
@@ -385,34 +502,35 @@ __global__ __launch_bounds__(kThreadsXY) void k_fwd_rho(const float2* __restrict
 // ---- adjoint kernels ---------------------------------------------------------
 
 // rho^_xi = c0^2 S^T y^{nt-1}, u^_xi = 0, W_xi = R2C(b_xi rho^_xi).
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_adj_init(const float* __restrict__ ylast, WaveBuffers B,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_init(const float* __restrict__ ylast, WaveBuffers B,
                                                          WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int tid = threadIdx.x;
   int z, xi;
-  slab_field_of_block<NZ>(blockIdx.x, z, xi);
+  slab_field_of_block(blockIdx.x, z, xi);
   const size_t rz = (size_t)z * D::SLAB_P, cz = (size_t)z * D::SLAB_C;
   float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
   float2* ub = reinterpret_cast<float2*>(B.u[xi]) + rz;
   const float2 zero = make_float2(0.f, 0.f);
   if (z != 0) {
-    for (int e = tid; e < D::SLAB_P; e += kThreadsXY) { rb[e] = zero; ub[e] = zero; }
-    for (int e = tid; e < D::SLAB_C; e += kThreadsXY) B.spec[xi][cz + e] = zero;
+    for (int e = tid; e < D::SLAB_P; e += NT) { rb[e] = zero; ub[e] = zero; }
+    for (int e = tid; e < D::SLAB_C; e += NT) B.spec[xi][cz + e] = zero;
     return;
   }
   const float2* y = reinterpret_cast<const float2*>(ylast);
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+  for (int e = tid; e < D::SLAB_P; e += NT) {
     const int yy = e / D::MX, n = e % D::MX;
-    const float2 r = cscale(y[e], sc.c2);
+    const float2 r = make_float2(y[e].x * sc.c2, y[e].y * sc.c2);
     rb[e] = r;
     ub[e] = zero;
     float b0, b1;
     if (xi == 0) { b0 = t.bx[2 * n]; b1 = t.bx[2 * n + 1]; }
     else if (xi == 1) { b0 = b1 = t.by[yy]; }
     else { b0 = b1 = t.bz[0]; }
-    S[yy * D::PITCH + n] = make_float2(b0 * r.x, b1 * r.y);
+    S[yy * D::PITCH + n] = widen<V>(make_float2(b0 * r.x, b1 * r.y));
   }
   __syncthreads();
   slab_r2c<NX, NY, NZ>(S, t, tid);
@@ -421,30 +539,39 @@ __global__ __launch_bounds__(kThreadsXY) void k_adj_init(const float* __restrict
 
 // u^_xi: uh = u^ + dt rho0 Dplus_xi(b rho^) (the pencil pass already applied the
 // multiplier), u^ <- a^2 uh, W_xi = R2C(a uh) in place.
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc) {
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int tid = threadIdx.x;
   int z, xi;
-  slab_field_of_block<NZ>(blockIdx.x, z, xi);
+  slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
-  load_spec<NX, NY, NZ>(S, B.spec[xi] + cz, 0, nullptr, tid);
+  load_spec<NX, NY, NZ>(S, B.spec[xi] + cz, 0, (const V*)nullptr, tid);
+  float2* ub = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
+  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
+  float2 uold[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (tid + i * NT < D::SLAB_P) uold[i] = ub[tid + i * NT];
   __syncthreads();
   slab_c2r<NX, NY, NZ>(S, t, tid);
-  float2* ub = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
   const float azz = t.az[z];
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (e >= D::SLAB_P) break;
     const int y = e / D::MX, n = e % D::MX;
-    const float2 g = S[y * D::PITCH + n];
+    const float2 g = narrow(S[y * D::PITCH + n]);
     float a0, a1;
     if (xi == 0) { a0 = t.ax[2 * n]; a1 = t.ax[2 * n + 1]; }
     else if (xi == 1) { a0 = a1 = t.ay[y]; }
     else { a0 = a1 = azz; }
-    const float2 uo = ub[e];
+    const float2 uo = uold[i];
     const float2 uh = make_float2(uo.x + sc.dt_rho0 * g.x, uo.y + sc.dt_rho0 * g.y);
     ub[e] = make_float2(a0 * a0 * uh.x, a1 * a1 * uh.y);
-    S[y * D::PITCH + n] = make_float2(a0 * uh.x, a1 * uh.y);
+    S[y * D::PITCH + n] = widen<V>(make_float2(a0 * uh.x, a1 * uh.y));
   }
   __syncthreads();
   slab_r2c<NX, NY, NZ>(S, t, tid);
@@ -453,80 +580,87 @@ __global__ __launch_bounds__(kThreadsXY) void k_adj_u(WaveBuffers B, WaveTables 
 
 // Pencil pass of the summed divergence: out = IFFT_z[ sum_xi kappa/N i k_xi
 // e^{-i k_xi dx/2} FFT_z(W_xi) ].
-template <int NX, int NY, int NZ>
+template <int NX, int NY, int NZ, typename V>
 __global__ __launch_bounds__(kThreadsZ) void k_zdiv_sum(const float2* __restrict__ W0,
                                                         const float2* __restrict__ W1,
                                                         const float2* __restrict__ W2,
                                                         float2* __restrict__ out, WaveTables t,
                                                         float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
+  using Sc = typename ScalarOf<V>::T;
   constexpr int TY = D::TY, W = 2 * TY;
-  __shared__ float2 T[NZ * W];
+  __shared__ V T[NZ * W];
+  const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  const float hx = t.hx[kx];
   for (int xi = 0; xi < 3; ++xi) {
     const float2* H = xi == 0 ? W0 : (xi == 1 ? W1 : W2);
-    for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-      const int z = e / TY, j = e % TY;
-      T[z * W + j] = H[((size_t)z * D::NKX + kx) * NY + p0 + j];
-    }
+    load_tile<NX, NY, NZ>(T, W, 0, H, kx, p0, tid);
     __syncthreads();
-    fft_forward<NZ, true>(T, TY, 1, W, t.tw_z, tid, kThreadsZ);
+    fft_forward<NZ, true>(T, TY, 1, W, tab.tw_z, tid, kThreadsZ);
     for (int e = tid; e < NZ * TY; e += kThreadsZ) {
       const int q = e / TY, j = e % TY;
-      const float hy = t.hy[p0 + j], hz = t.hz[q];
-      const float h = sqrtf(hx * hx + hy * hy + hz * hz);
-      const float kap = (h > 0.f ? sinf(h) / h : 1.f) * inv_ntot;
-      const float2 m = xi == 0 ? t.mmx[kx] : (xi == 1 ? t.mmy[p0 + j] : t.mmz[q]);
-      const float2 v = cmul(cscale(T[q * W + j], kap), m);
+      const Sc kap = kappa_at<V>(tab, kx, p0 + j, q, (Sc)inv_ntot);
+      const V m = xi == 0 ? tab.mmx[kx] : (xi == 1 ? tab.mmy[p0 + j] : tab.mmz[q]);
+      const V v = cmul(cscale(T[q * W + j], kap), m);
       T[q * W + TY + j] = xi == 0 ? v : cadd(T[q * W + TY + j], v);
     }
     __syncthreads();
   }
-  fft_inverse<NZ, true>(T + TY, TY, 1, W, t.tw_z, tid, kThreadsZ);
-  for (int e = tid; e < NZ * TY; e += kThreadsZ) {
-    const int z = e / TY, j = e % TY;
-    out[((size_t)z * D::NKX + kx) * NY + p0 + j] = T[z * W + TY + j];
-  }
+  fft_inverse<NZ, true>(T + TY, TY, 1, W, tab.tw_z, tid, kThreadsZ);
+  store_tile<NX, NY, NZ>(T, W, TY, out, kx, p0, tid);
 }
 
 // rho^_xi <- b^2 rho^_xi + c0^2 dt/rho0 q + c0^2 S^T y^n; then W_xi = R2C(b rho^_xi),
 // or on the last (final != 0) step W_xi = R2C(u^_xi) for the initial-condition transpose.
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_adj_rho(const float2* __restrict__ Qs, WaveBuffers B,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_rho(const float2* __restrict__ Qs, WaveBuffers B,
                                                         const float* __restrict__ yplane, WaveTables t,
                                                         WaveScalars sc, int final_step) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int tid = threadIdx.x;
   int z, xi;
-  slab_field_of_block<NZ>(blockIdx.x, z, xi);
+  slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  load_spec<NX, NY, NZ>(S, Qs + cz, 0, nullptr, tid);
-  __syncthreads();
-  slab_c2r<NX, NY, NZ>(S, t, tid);
+  load_spec<NX, NY, NZ>(S, Qs + cz, 0, (const V*)nullptr, tid);
   float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
   const float2* ub = reinterpret_cast<const float2*>(B.u[xi]) + rz;
   const float2* y = reinterpret_cast<const float2*>(yplane);
+  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
+  float2 rold[EPT], extra[EPT];   // extra: source plane (z = 0) or u^ (final step)
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (e < D::SLAB_P) {
+      rold[i] = rb[e];
+      extra[i] = final_step ? ub[e] : (z == 0 ? y[e] : make_float2(0.f, 0.f));
+    }
+  }
+  __syncthreads();
+  slab_c2r<NX, NY, NZ>(S, t, tid);
   const float qs = sc.c2 * sc.dt_over_rho0;
   const float bzz = t.bz[z];
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (e >= D::SLAB_P) break;
     const int yy = e / D::MX, n = e % D::MX;
-    const float2 q = S[yy * D::PITCH + n];
+    const float2 q = narrow(S[yy * D::PITCH + n]);
     float b0, b1;
     if (xi == 0) { b0 = t.bx[2 * n]; b1 = t.bx[2 * n + 1]; }
     else if (xi == 1) { b0 = b1 = t.by[yy]; }
     else { b0 = b1 = bzz; }
-    const float2 ro = rb[e];
+    const float2 ro = rold[i];
     float2 rn = make_float2(b0 * b0 * ro.x + qs * q.x, b1 * b1 * ro.y + qs * q.y);
     if (z == 0) {
-      const float2 s = y[e];
-      rn.x += sc.c2 * s.x;
-      rn.y += sc.c2 * s.y;
+      const float2 sy = final_step ? y[e] : extra[i];
+      rn.x += sc.c2 * sy.x;
+      rn.y += sc.c2 * sy.y;
     }
     rb[e] = rn;
-    S[yy * D::PITCH + n] = final_step ? ub[e] : make_float2(b0 * rn.x, b1 * rn.y);
+    S[yy * D::PITCH + n] = widen<V>(final_step ? extra[i] : make_float2(b0 * rn.x, b1 * rn.y));
   }
   __syncthreads();
   slab_r2c<NX, NY, NZ>(S, t, tid);
@@ -534,16 +668,17 @@ __global__ __launch_bounds__(kThreadsXY) void k_adj_rho(const float2* __restrict
 }
 
 // p = (rho^_x + rho^_y + rho^_z)/(3 c0^2) - dt/(2 rho0) sum_xi Dminus_xi u^_xi.
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreadsXY) void k_adj_final(const float2* __restrict__ Qs, WaveBuffers B,
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_final(const float2* __restrict__ Qs, WaveBuffers B,
                                                           float* __restrict__ pout, WaveTables t,
                                                           WaveScalars sc, int with_velocity) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ float2 S[NY * D::PITCH];
+  constexpr int NT = SlabThreads<V>::value;
+  __shared__ V S[NY * D::PITCH];
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
   if (with_velocity) {
-    load_spec<NX, NY, NZ>(S, Qs + cz, 0, nullptr, tid);
+    load_spec<NX, NY, NZ>(S, Qs + cz, 0, (const V*)nullptr, tid);
     __syncthreads();
     slab_c2r<NX, NY, NZ>(S, t, tid);
   }
@@ -551,12 +686,12 @@ __global__ __launch_bounds__(kThreadsXY) void k_adj_final(const float2* __restri
   const float2* r1 = reinterpret_cast<const float2*>(B.rho[1]) + rz;
   const float2* r2 = reinterpret_cast<const float2*>(B.rho[2]) + rz;
   float2* p = reinterpret_cast<float2*>(pout) + rz;
-  for (int e = tid; e < D::SLAB_P; e += kThreadsXY) {
+  for (int e = tid; e < D::SLAB_P; e += NT) {
     const int y = e / D::MX, n = e % D::MX;
     const float2 a = r0[e], b = r1[e], c = r2[e];
     float2 v = make_float2((a.x + b.x + c.x) * sc.inv_3c2, (a.y + b.y + c.y) * sc.inv_3c2);
     if (with_velocity) {
-      const float2 g = S[y * D::PITCH + n];
+      const float2 g = narrow(S[y * D::PITCH + n]);
       v.x -= sc.half_dt_over_rho0 * g.x;
       v.y -= sc.half_dt_over_rho0 * g.y;
     }
@@ -578,64 +713,68 @@ inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
   }
 }
 
-template <int NX, int NY, int NZ>
+template <int NX, int NY, int NZ, typename V>
 hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
                         const float* p0, float* planes, int nt, hipStream_t st, KernelTimer* kt) {
   using D = Dims<NX, NY, NZ>;
+  constexpr int NT = SlabThreads<V>::value;
   const size_t npix = (size_t)NX * NY;
-  k_fwd_init<NX, NY, NZ><<<NZ, kThreadsXY, 0, st>>>(p0, B, planes, t, sc);
+  k_fwd_init<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(p0, B, planes, t, sc);
   for (int n = 0; n < nt - 1; ++n) {
     timed(kt, K_ZGRAD, st, [&] {
-      k_zgrad<NX, NY, NZ><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], t, sc.inv_ntot);
+      k_zgrad<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], t, sc.inv_ntot);
     });
     timed(kt, K_FWD_U, st, [&] {
-      k_fwd_u<NX, NY, NZ><<<3 * NZ, kThreadsXY, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], B.spec[1], B,
-                                                          t, sc, n == 0 ? 1 : 0);
+      k_fwd_u<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3],
+                                                             B.spec[1], B, t, sc, n == 0 ? 1 : 0);
     });
     timed(kt, K_ZDIV, st, [&] {
-      k_zmul<NX, NY, NZ, false><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], t,
-                                                                          sc.inv_ntot);
+      k_zmul<NX, NY, NZ, V, false><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], t,
+                                                                             sc.inv_ntot);
     });
     timed(kt, K_FWD_RHO, st, [&] {
-      k_fwd_rho<NX, NY, NZ><<<NZ, kThreadsXY, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0],
-                                                        planes + (size_t)(n + 1) * npix, t, sc);
+      k_fwd_rho<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0],
+                                                           planes + (size_t)(n + 1) * npix, t, sc);
     });
   }
   return hipGetLastError();
 }
 
-template <int NX, int NY, int NZ>
+template <int NX, int NY, int NZ, typename V>
 hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
                         const float* planes, float* p, int nt, hipStream_t st, KernelTimer* kt) {
   using D = Dims<NX, NY, NZ>;
+  constexpr int NT = SlabThreads<V>::value;
   const size_t npix = (size_t)NX * NY;
-  k_adj_init<NX, NY, NZ><<<3 * NZ, kThreadsXY, 0, st>>>(planes + (size_t)(nt - 1) * npix, B, t, sc);
+  k_adj_init<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(planes + (size_t)(nt - 1) * npix, B, t, sc);
   if (nt == 1) {
-    k_adj_final<NX, NY, NZ><<<NZ, kThreadsXY, 0, st>>>(B.spec[3], B, p, t, sc, 0);
+    k_adj_final<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(B.spec[3], B, p, t, sc, 0);
     return hipGetLastError();
   }
   for (int n = nt - 2; n >= 0; --n) {
     timed(kt, K_ZGRAD_ADJ, st, [&] {
-      k_zmul<NX, NY, NZ, true><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], t,
-                                                                         sc.inv_ntot);
+      k_zmul<NX, NY, NZ, V, true><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], t,
+                                                                            sc.inv_ntot);
     });
-    timed(kt, K_ADJ_U, st, [&] { k_adj_u<NX, NY, NZ><<<3 * NZ, kThreadsXY, 0, st>>>(B, t, sc); });
+    timed(kt, K_ADJ_U, st, [&] { k_adj_u<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B, t, sc); });
     timed(kt, K_ZDIV_SUM, st, [&] {
-      k_zdiv_sum<NX, NY, NZ><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], t,
-                                                             sc.inv_ntot);
+      k_zdiv_sum<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], t,
+                                                                sc.inv_ntot);
     });
     timed(kt, K_ADJ_RHO, st, [&] {
-      k_adj_rho<NX, NY, NZ><<<3 * NZ, kThreadsXY, 0, st>>>(B.spec[3], B, planes + (size_t)n * npix, t, sc,
-                                                           n == 0 ? 1 : 0);
+      k_adj_rho<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B.spec[3], B, planes + (size_t)n * npix, t, sc,
+                                                              n == 0 ? 1 : 0);
     });
   }
-  k_zdiv_sum<NX, NY, NZ><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], t,
-                                                         sc.inv_ntot);
-  k_adj_final<NX, NY, NZ><<<NZ, kThreadsXY, 0, st>>>(B.spec[3], B, p, t, sc, 1);
+  k_zdiv_sum<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], t,
+                                                            sc.inv_ntot);
+  k_adj_final<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(B.spec[3], B, p, t, sc, 1);
   return hipGetLastError();
 }
 
-#define PAT_WAVE_IMPL(N) {N, N, N, &wave_forward<N, N, N>, &wave_adjoint<N, N, N>}
+#define PAT_WAVE_IMPL(N)                                                            \
+  {N, N, N, {&wave_forward<N, N, N, float2>, &wave_forward<N, N, N, double2>},     \
+   {&wave_adjoint<N, N, N, float2>, &wave_adjoint<N, N, N, double2>}}
 
 static const WaveImpl kWaveImpls[] = {
     PAT_WAVE_IMPL(16),

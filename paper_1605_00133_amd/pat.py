@@ -60,6 +60,7 @@ SIGNATURES = {
                                   C.POINTER(_P)]),
     "pat_plan_destroy": (C.c_int, [_P]),
     "pat_plan_set_stream": (C.c_int, [_P, _P]),
+    "pat_plan_set_fft_precision": (C.c_int, [_P, C.c_int32]),
     "pat_forward": (C.c_int, [_P, _P, _P]),
     "pat_adjoint": (C.c_int, [_P, _P, _P]),
     "pat_sample": (C.c_int, [_P, _P, _P]),
@@ -84,9 +85,16 @@ _lib = None
 
 
 def lib():
-    """Load libpat.so (raises if it has not been built)."""
+    """Load libpat.so (raises if it has not been built).
+
+    torch is imported first so that its bundled HIP runtime is the only one in
+    the process: libpat.so then binds to it by soname instead of mapping a
+    second runtime from /opt/rocm, which would fail to initialise next to
+    torch's.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (load order matters, see docstring)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1605_00133_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -183,6 +191,9 @@ class Plan:
     def plane_shape(self):
         g = self.grid
         return (g.nt, g.ny, g.nx)
+
+    def set_fft_precision(self, bits):
+        _check(lib().pat_plan_set_fft_precision(self.handle, int(bits)))
 
     def sync_stream(self):
         stream = self.torch.cuda.current_stream(self.device).cuda_stream

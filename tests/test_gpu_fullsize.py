@@ -1,0 +1,66 @@
+"""Full-size (128^3, Nt = 740) GPU parity of A and A^T, in the configuration the
+benchmark times, on outputs sampled from the FP64 oracle.
+
+The oracle values were written by tests/golden/make_operator_fixtures.py
+(oracle only): 32 data columns of C A p0 for all 740 samples, and two z-slices
+of A^T C^T y. Tolerance: 1e-5 relative L2 over the sampled entries.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from gpu_cases import empty, gaussian_data, rel_l2, to_dev, to_host
+from synthetic import vessel_phantom
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+N, NT, P = 128, 740, 8
+TOL_OP = 1e-5
+
+
+def _fixture(case):
+    path = os.path.join(GOLDEN, f"op128_{case}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {path} not generated")
+    return np.load(path)
+
+
+def _plan(kind):
+    from paper_1605_00133_amd import pat as Pb
+    g = Pb.make_grid(N, N, N, 100e-6, 1500.0, 20e-9, NT, P)
+    if kind == "points":
+        return Pb.Plan(g, "points", 2048, Pb.pat_make_rsp_mask(N * N, 2048, 2))
+    perm, rows = Pb.pat_make_shd_pattern(N * N, 2048, 4)
+    return Pb.Plan(g, "hadamard", 2048, rows, perm)
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard"])
+def test_forward_128(kind):
+    from paper_1605_00133_amd import pat as Pb
+    fx = _fixture(f"forward_{kind}")
+    plan = _plan(kind)
+    p0 = vessel_phantom((N, N, N), P, 24, 1.0, 4.0, 1)
+    f = empty(plan.data_shape)
+    Pb.pat_forward(plan, to_dev(p0), f)
+    got = to_host(f)[:, fx["cols"]]
+    err = rel_l2(got, fx["values"])
+    full_norm_err = abs(np.linalg.norm(to_host(f)) - float(fx["norm"])) / float(fx["norm"])
+    print(f"128^3 forward {kind}: rel L2 over sampled columns {err:.3e}; |f| rel diff {full_norm_err:.3e}")
+    assert err < TOL_OP
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard"])
+def test_adjoint_128(kind):
+    from paper_1605_00133_amd import pat as Pb
+    fx = _fixture(f"adjoint_{kind}")
+    plan = _plan(kind)
+    y = gaussian_data((NT, 2048), int(fx["data_seed"]))
+    p = empty(plan.vol_shape)
+    Pb.pat_adjoint(plan, to_dev(y), p)
+    got = to_host(p)[fx["zs"]]
+    err = rel_l2(got, fx["values"])
+    print(f"128^3 adjoint {kind} (white-noise data): rel L2 over sampled slices {err:.3e}")
+    assert err < TOL_OP

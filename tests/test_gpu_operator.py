@@ -17,25 +17,27 @@ pytestmark = pytest.mark.gpu
 TOL_OP = 1e-5
 
 
-def _fwd_case(n, nt, kind, pml=8, x=None):
+def _fwd_case(n, nt, kind, pml=8, x=None, bits=64):
     g = oracle_grid(n, nt, pml)
     smp = oracle_sampling(kind, n)
     x = phantom(n, pml) if x is None else x
     ref = apply_c(oracle.WaveOperator(g).forward_planes(x), smp)
     from paper_1605_00133_amd import pat as P
     plan = gpu_plan(n, nt, smp, pml)
+    plan.set_fft_precision(bits)
     f = empty(plan.data_shape)
     P.pat_forward(plan, to_dev(x), f)
     return to_host(f), ref
 
 
-def _adj_case(n, nt, kind, pml=8, seed=5):
+def _adj_case(n, nt, kind, pml=8, seed=5, bits=64):
     g = oracle_grid(n, nt, pml)
     smp = oracle_sampling(kind, n)
     y = gaussian_data((nt, smp.mc), seed)
     ref = oracle.WaveOperator(g).adjoint_planes(apply_ct(y, smp, n, n))
     from paper_1605_00133_amd import pat as P
     plan = gpu_plan(n, nt, smp, pml)
+    plan.set_fft_precision(bits)
     p = empty(plan.vol_shape)
     P.pat_adjoint(plan, to_dev(y), p)
     return to_host(p), ref
@@ -57,6 +59,17 @@ def test_adjoint_matches_oracle(n, nt, kind, pml):
     err = rel_l2(got, ref)
     print(f"adjoint {n}^3 nt={nt} {kind}: rel L2 vs FP64 = {err:.3e}")
     assert err < TOL_OP
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard"])
+def test_fp32_butterfly_variant(kind):
+    """The FP32-arithmetic variant of the propagator (pat_plan_set_fft_precision(32)) at 32^3."""
+    got, ref = _fwd_case(32, 190, kind, bits=32)
+    e1 = rel_l2(got, ref)
+    got, ref = _adj_case(32, 190, kind, bits=32)
+    e2 = rel_l2(got, ref)
+    print(f"FP32 butterflies 32^3 {kind}: forward {e1:.3e}, adjoint {e2:.3e}")
+    assert e1 < TOL_OP and e2 < TOL_OP
 
 
 def test_forward_without_pml_closed_form_random_input():

@@ -170,69 +170,72 @@ __device__ __forceinline__ void dft_r(V* a) {
   else if constexpr (R == 16) dft16<INV>(a);
 }
 
-// ---- one radix stage over nseq sequences ------------------------------------
-// Element n of sequence q lives at buf[q*seq_stride + n*elem_stride].
-// SEQ_FAST: consecutive threads take consecutive sequences (use when sequences
-// are adjacent in LDS, i.e. seq_stride == 1); otherwise consecutive butterflies
-// of one sequence (use when elem_stride == 1). tw: the L-point twiddle table
-// exp(-2 pi i j / L), j < L, in the arithmetic type.
-template <int L, int S, bool INV, bool SEQ_FAST, typename V>
-__device__ __forceinline__ void fft_stage(V* buf, int nseq, int seq_stride, int elem_stride,
-                                          const V* __restrict__ tw, int tid, int nthr) {
+// ---- one radix stage over NSEQ sequences ------------------------------------
+// Element n of sequence q lives at buf[q*SS + n*ES]. All geometry is compile
+// time, so the butterfly loop is fully unrolled and the LDS reads of every
+// butterfly a thread owns are issued together. SEQ_FAST: consecutive threads
+// take consecutive sequences (use when SS == 1); otherwise consecutive
+// butterflies of one sequence (use when ES == 1). tw: the L-point twiddle
+// table exp(-2 pi i j / L), j < L, in the arithmetic type (an LDS copy).
+template <int L, int S, bool INV, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
+__device__ __forceinline__ void fft_stage(V* buf, const V* tw, int tid) {
   constexpr int R = fft_radix(L, S);
   constexpr int LS = fft_sublen(L, S);
   constexpr int M = LS / R;
   constexpr int NB = L / R;
   constexpr int TWS = L / LS;
-  const int total = nseq * NB;
-  for (int w = tid; w < total; w += nthr) {
-    int q, j;
-    if (SEQ_FAST) { q = w % nseq; j = w / nseq; }
-    else { j = w % NB; q = w / NB; }
-    const int blk = j / M, n1 = j % M;
-    V* base = buf + q * seq_stride + (blk * LS + n1) * elem_stride;
-    V a[R];
+  constexpr int TOTAL = NSEQ * NB;
+  constexpr int IT = (TOTAL + NT - 1) / NT;
 #pragma unroll
-    for (int m = 0; m < R; ++m) a[m] = base[m * M * elem_stride];
-    if constexpr (!INV) {
-      dft_r<R, false>(a);
-      if constexpr (M > 1) {
+  for (int i = 0; i < IT; ++i) {
+    const int w = tid + i * NT;
+    if (TOTAL % NT == 0 || w < TOTAL) {
+      int q, j;
+      if (SEQ_FAST) { q = w % NSEQ; j = w / NSEQ; }
+      else { j = w % NB; q = w / NB; }
+      const int blk = j / M, n1 = j % M;
+      V* base = buf + q * SS + (blk * LS + n1) * ES;
+      V a[R];
 #pragma unroll
-        for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw[TWS * n1 * k]);
+      for (int m = 0; m < R; ++m) a[m] = base[m * M * ES];
+      if constexpr (!INV) {
+        dft_r<R, false>(a);
+        if constexpr (M > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw[TWS * n1 * k]);
+        }
+      } else {
+        if constexpr (M > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) a[k] = cmulconj(a[k], tw[TWS * n1 * k]);
+        }
+        dft_r<R, true>(a);
       }
-    } else {
-      if constexpr (M > 1) {
 #pragma unroll
-        for (int k = 1; k < R; ++k) a[k] = cmulconj(a[k], tw[TWS * n1 * k]);
-      }
-      dft_r<R, true>(a);
+      for (int m = 0; m < R; ++m) base[m * M * ES] = a[m];
     }
-#pragma unroll
-    for (int m = 0; m < R; ++m) base[m * M * elem_stride] = a[m];
   }
 }
 
 // Forward transform (natural in, digit-reversed out). Caller syncs before; ends synced.
-template <int L, bool SEQ_FAST, typename V>
-__device__ __forceinline__ void fft_forward(V* buf, int nseq, int seq_stride, int elem_stride,
-                                            const V* __restrict__ tw, int tid, int nthr) {
-  fft_stage<L, 0, false, SEQ_FAST>(buf, nseq, seq_stride, elem_stride, tw, tid, nthr);
+template <int L, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
+__device__ __forceinline__ void fft_forward(V* buf, const V* tw, int tid) {
+  fft_stage<L, 0, false, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
   __syncthreads();
   if constexpr (fft_nstages(L) > 1) {
-    fft_stage<L, 1, false, SEQ_FAST>(buf, nseq, seq_stride, elem_stride, tw, tid, nthr);
+    fft_stage<L, 1, false, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
     __syncthreads();
   }
 }
 
 // Inverse transform (digit-reversed in, natural out). Caller syncs before; ends synced.
-template <int L, bool SEQ_FAST, typename V>
-__device__ __forceinline__ void fft_inverse(V* buf, int nseq, int seq_stride, int elem_stride,
-                                            const V* __restrict__ tw, int tid, int nthr) {
+template <int L, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
+__device__ __forceinline__ void fft_inverse(V* buf, const V* tw, int tid) {
   if constexpr (fft_nstages(L) > 1) {
-    fft_stage<L, 1, true, SEQ_FAST>(buf, nseq, seq_stride, elem_stride, tw, tid, nthr);
+    fft_stage<L, 1, true, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
     __syncthreads();
   }
-  fft_stage<L, 0, true, SEQ_FAST>(buf, nseq, seq_stride, elem_stride, tw, tid, nthr);
+  fft_stage<L, 0, true, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
   __syncthreads();
 }
 

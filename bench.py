@@ -38,7 +38,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("wave_kernels.hip", "fft_lds.hpp", "wave_common.hpp"):
+    for f in ("wave_kernels.hip", "fft_radix.hpp", "wave_common.hpp"):
         with open(os.path.join(ROOT, "paper_1605_00133_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -1,28 +1,30 @@
-// In-place radix-R FFT stages on complex data held in LDS, for gfx950.
+// Small DFTs in registers and the two-stage split of the propagator's FFTs, for gfx950.
 //
-// The wave propagator needs many small power-of-two transforms (lengths
-// 4..128) along each axis of a 3D grid. A length-L transform is split into at
-// most two radix stages (4, 8, 16, 8x4, 8x8, 16x8); every thread loads R
-// elements of one butterfly from LDS, runs the R-point DFT in registers and
-// writes the R results back to the same LDS slots. Because each butterfly reads
-// and writes its own slots, a stage needs no second buffer, only a barrier
-// before the next.
+// The wave propagator needs power-of-two transforms of lengths 8..128 along
+// each axis of a 3D grid. A length-L transform is split as L = R0 * M
+// (R0 = 16 for L = 16, 128; 8 for L = 8, 32, 64; M = L / R0, M = 1 for L <= 16):
 //
-//  * forward: decimation in frequency, natural-order input, output X[k] at
-//    position pos(k) (digit-reversed), unnormalised, sign -1;
-//  * inverse: the exact reverse of the forward stages (conjugate twiddles, then
-//    the conjugate DFT), digit-reversed input, natural-order output,
-//    unnormalised, sign +1; inverse(forward(x)) = L x.
+//  * forward stage 0 (decimation in frequency): for every n1 < M the R0 values
+//    x[n1 + M m], m < R0, go through an R0-point DFT and are multiplied by
+//    w_L^(n1 k); result k is kept at index n1 + M k;
+//  * forward stage 1: every block b < R0 (indices M b + j, j < M) goes through
+//    an M-point DFT; frequency b + R0 k1 ends at position M b + k1.
 //
-// Pointwise spectral work between a forward and an inverse transform therefore
-// never permutes data: it only needs freq(p), the frequency held at position p.
+// A thread owns one butterfly of a stage with all its values in registers;
+// stages exchange data through LDS once. The inverse runs the same two stages
+// backwards (conjugate DFTs and twiddles), reading positions and producing
+// natural order, unnormalised, so inverse(forward(x)) = L x. Pointwise
+// spectral work between a forward and an inverse transform never permutes
+// data: it only needs freq(p), the frequency held at position p.
 //
 // The arithmetic type V is float2 or double2. Data in HBM is always float2;
-// with V = double2 a transform keeps FP64 values in registers and LDS and
-// rounds to FP32 only when its result leaves the kernel.
+// with V = double2 the values stay FP64 in registers and LDS and are rounded to
+// FP32 only when they leave the kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 namespace pat {
 
@@ -165,78 +167,31 @@ __device__ __forceinline__ void dft16(V* a) {
 
 template <int R, bool INV, typename V>
 __device__ __forceinline__ void dft_r(V* a) {
-  if constexpr (R == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
+  if constexpr (R == 1) (void)a;
+  else if constexpr (R == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
   else if constexpr (R == 8) dft8<INV>(a);
   else if constexpr (R == 16) dft16<INV>(a);
 }
 
-// ---- one radix stage over NSEQ sequences ------------------------------------
-// Element n of sequence q lives at buf[q*SS + n*ES]. All geometry is compile
-// time, so the butterfly loop is fully unrolled and the LDS reads of every
-// butterfly a thread owns are issued together. SEQ_FAST: consecutive threads
-// take consecutive sequences (use when SS == 1); otherwise consecutive
-// butterflies of one sequence (use when ES == 1). tw: the L-point twiddle
-// table exp(-2 pi i j / L), j < L, in the arithmetic type (an LDS copy).
-template <int L, int S, bool INV, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
-__device__ __forceinline__ void fft_stage(V* buf, const V* tw, int tid) {
-  constexpr int R = fft_radix(L, S);
-  constexpr int LS = fft_sublen(L, S);
-  constexpr int M = LS / R;
-  constexpr int NB = L / R;
-  constexpr int TWS = L / LS;
-  constexpr int TOTAL = NSEQ * NB;
-  constexpr int IT = (TOTAL + NT - 1) / NT;
+// Stage-0 twiddles of butterfly n1: a[k] *= w^k (forward) or conj(w)^k (inverse)
+// for k = 1..R-1, w = w_L^n1 = tw[n1] from the L-point table exp(-2 pi i j / L).
+// In FP64 the powers are built by repeated multiplication (a relative error of
+// a few 1e-16, far below the FP32 storage rounding) so one table read serves
+// the whole butterfly; in FP32 every power is read from the table.
+template <int R, bool INV, typename V>
+__device__ __forceinline__ void stage_twiddle(V* a, const V* tw, int n1) {
+  if constexpr (std::is_same<V, double2>::value) {
+    const V w = tw[n1];
+    V wk = w;
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * NT;
-    if (TOTAL % NT == 0 || w < TOTAL) {
-      int q, j;
-      if (SEQ_FAST) { q = w % NSEQ; j = w / NSEQ; }
-      else { j = w % NB; q = w / NB; }
-      const int blk = j / M, n1 = j % M;
-      V* base = buf + q * SS + (blk * LS + n1) * ES;
-      V a[R];
-#pragma unroll
-      for (int m = 0; m < R; ++m) a[m] = base[m * M * ES];
-      if constexpr (!INV) {
-        dft_r<R, false>(a);
-        if constexpr (M > 1) {
-#pragma unroll
-          for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw[TWS * n1 * k]);
-        }
-      } else {
-        if constexpr (M > 1) {
-#pragma unroll
-          for (int k = 1; k < R; ++k) a[k] = cmulconj(a[k], tw[TWS * n1 * k]);
-        }
-        dft_r<R, true>(a);
-      }
-#pragma unroll
-      for (int m = 0; m < R; ++m) base[m * M * ES] = a[m];
+    for (int k = 1; k < R; ++k) {
+      a[k] = INV ? cmulconj(a[k], wk) : cmul(a[k], wk);
+      if (k + 1 < R) wk = cmul(wk, w);
     }
+  } else {
+#pragma unroll
+    for (int k = 1; k < R; ++k) a[k] = INV ? cmulconj(a[k], tw[n1 * k]) : cmul(a[k], tw[n1 * k]);
   }
-}
-
-// Forward transform (natural in, digit-reversed out). Caller syncs before; ends synced.
-template <int L, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
-__device__ __forceinline__ void fft_forward(V* buf, const V* tw, int tid) {
-  fft_stage<L, 0, false, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
-  __syncthreads();
-  if constexpr (fft_nstages(L) > 1) {
-    fft_stage<L, 1, false, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
-    __syncthreads();
-  }
-}
-
-// Inverse transform (digit-reversed in, natural out). Caller syncs before; ends synced.
-template <int L, bool SEQ_FAST, int NSEQ, int SS, int ES, int NT, typename V>
-__device__ __forceinline__ void fft_inverse(V* buf, const V* tw, int tid) {
-  if constexpr (fft_nstages(L) > 1) {
-    fft_stage<L, 1, true, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
-    __syncthreads();
-  }
-  fft_stage<L, 0, true, SEQ_FAST, NSEQ, SS, ES, NT>(buf, tw, tid);
-  __syncthreads();
 }
 
 }  // namespace pat

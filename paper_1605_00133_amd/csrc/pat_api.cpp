@@ -12,7 +12,7 @@
 #include <cstring>
 #include <vector>
 
-#include "fft_lds.hpp"
+#include "fft_radix.hpp"
 #include "pat_internal.hpp"
 #include "sample_common.hpp"
 #include "vec_common.hpp"

@@ -10,21 +10,25 @@
 //
 // Every 3D FFT is done in two global passes:
 //   slab kernels (one workgroup per z-slab): 2D real<->complex transform of the
-//     slab in LDS (x: packed half-length complex FFT plus real-FFT
-//     post-processing; y: column FFT), fused with the real-space update of the
-//     state fields;
+//     slab, fused with the real-space update of the state fields;
 //   pencil kernels (one workgroup per 16 ky columns of one kx, all z): z
-//     transform in LDS, the k-space multipliers, inverse z transform.
+//     transform, the k-space multipliers, inverse z transform.
 // Slab spectra live in HBM as float2 [z][kx][ky_pos] (kx = 0..nx/2 natural, ky
 // in digit-reversed position order), so pencil tiles read 128-byte rows and no
-// kernel ever permutes data. The state fields are float in HBM and updated in
-// FP32; the transforms run in the arithmetic type V (float2, or double2 for
-// FP64 butterflies with a single FP32 rounding per pass).
+// kernel ever permutes data.
 //
-// Latency: every loop has a compile-time trip count and is unrolled, global
-// loads of a thread are issued together, and the small tables a kernel needs
-// (twiddles, PML profiles, wavenumbers, derivative factors) are copied to LDS
-// at kernel start, so no butterfly or pointwise step waits on a global load.
+// Every butterfly runs in registers: a thread loads all values of its
+// butterfly (from HBM or LDS), transforms them and passes them on; LDS is only
+// the exchange between the two radix stages of a dimension and between the x
+// and y passes. A slab round trip C2R -> update -> R2C therefore crosses LDS
+// six times, a pencil round trip twice, and the real-space update works on the
+// registers the inverse x stage left behind. Access patterns are chosen so
+// that consecutive lanes touch consecutive LDS slots (odd row pitch), which
+// keeps every exchange free of bank conflicts.
+//
+// The state fields are float in HBM and updated in FP32; the transforms run in
+// the arithmetic type V (float2, or double2 for FP64 butterflies with a single
+// FP32 rounding per pass).
 //
 // Forward step = pencil(grad: 1 in, 2 out) -> slab(u: per component) ->
 // pencil(div: per component) -> slab(rho, p, sensor plane, R2C of p).
@@ -32,16 +36,15 @@
 // -> pencil(sum of the three divergences: 3 in, 1 out) -> slab(rho^ + source).
 #include <hip/hip_runtime.h>
 
-#include "fft_lds.hpp"
+#include "fft_radix.hpp"
 #include "wave_common.hpp"
 
 namespace pat {
 
 constexpr int kThreadsZ = 128;
+constexpr int kThreadsSlab = 512;
 
-// threads per slab workgroup (8 waves): FP32 slabs of 128^2 take 66.5 KB of LDS
-// (two workgroups per CU), FP64 slabs 133 KB (one per CU, up to 256 VGPRs).
-template <typename V> struct SlabThreads { static constexpr int value = 512; };
+__host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 template <int NX, int NY, int NZ>
 struct Dims {
@@ -50,15 +53,33 @@ struct Dims {
   static constexpr int PITCH = NKX;          // LDS row pitch (complex), odd
   static constexpr int SLAB_C = NKX * NY;    // complex values per slab spectrum
   static constexpr int SLAB_P = NY * MX;     // float2 pairs per real slab
+  // two-stage splits L = R0 * M of the x (packed), y and z transforms
+  static constexpr int RX0 = fft_radix(MX, 0), MXB = MX / RX0;
+  static constexpr int RY0 = fft_radix(NY, 0), MYB = NY / RY0;
+  static constexpr int RZ0 = fft_radix(NZ, 0), MZB = NZ / RZ0;
+  // slab work items per phase and their loop counts over kThreadsSlab threads
+  static constexpr int NY1 = NKX * RY0;      // y stage-1 butterflies (M-point)
+  static constexpr int NY0 = NKX * MYB;      // y stage-0 butterflies (R0-point)
+  static constexpr int NXP = NY * (RX0 / 2); // x stage-1 pairs of butterflies (+ real-FFT split)
+  static constexpr int NX0 = NY * MXB;       // x stage-0 butterflies
+  static constexpr int IY1 = cdiv(NY1, kThreadsSlab), IY0 = cdiv(NY0, kThreadsSlab);
+  static constexpr int IXP = cdiv(NXP, kThreadsSlab), IX0 = cdiv(NX0, kThreadsSlab);
+  // pencil tiles
   static constexpr int TY = NY >= 16 ? 16 : NY;
   static constexpr int NTILE = NKX * (NY / TY);
-  static constexpr int ZIT = (NZ * TY + kThreadsZ - 1) / kThreadsZ;   // tile elements per z thread
-  static constexpr int TWN = MX + NKX + NY;  // slab twiddles: MX-point, real-FFT, NY-point
-  // rows per chunk of the real-FFT pre/post-processing (bounds its registers)
-  static constexpr int NP = MX / 2 + 1;
-  static constexpr int RC0 = 1024 / NP >= NY ? NY : (1024 / NP >= 64 ? 64 : 1024 / NP >= 32 ? 32 : 1024 / NP >= 16 ? 16 : 8);
-  static constexpr int RC = RC0 > NY ? NY : RC0;
+  static constexpr int NZ0 = TY * MZB;       // z stage-0 butterflies per tile
+  static constexpr int NZ1 = TY * RZ0;       // z stage-1 butterflies per tile
+  static constexpr int IZ0 = cdiv(NZ0, kThreadsZ), IZ1 = cdiv(NZ1, kThreadsZ);
+  static_assert(RX0 >= 4 && RX0 % 2 == 0, "x split needs an even first radix");
 };
+
+// Register arrays of the real-space layout (per slot i, value m) and of a pencil tile.
+template <int NX, int NY, int NZ>
+using RealRegs = float2[Dims<NX, NY, NZ>::IX0][Dims<NX, NY, NZ>::RX0];
+template <int NX, int NY, int NZ>
+using ZRegs = float2[Dims<NX, NY, NZ>::IZ0][Dims<NX, NY, NZ>::RZ0];
+template <int NX, int NY, int NZ, typename V>
+using ZVals = V[Dims<NX, NY, NZ>::IZ1][Dims<NX, NY, NZ>::MZB];
 
 template <typename V> struct TabSel;
 template <> struct TabSel<float2> {
@@ -95,265 +116,518 @@ __device__ __forceinline__ double sinc_of_sq(double s) {
 }
 
 // ---- LDS workspace of a slab workgroup ---------------------------------------
+// S holds the slab as rows y (0..NY-1) of PITCH complex slots; column kx of the
+// spectrum is S[.][kx]. The same rows hold the packed real row (index n, the
+// pair x = 2n, 2n+1) and the intermediate stage of the x transform.
 template <int NX, int NY, int NZ, typename V>
 struct SlabLds {
   using D = Dims<NX, NY, NZ>;
-  V S[NY * D::PITCH];     // the slab
-  V tw[D::TWN];           // [0, MX): MX-point, [MX, MX+NKX): exp(-2 pi i k/NX), then NY-point
-  float px[NX];           // PML profile along x of the component handled
-  float py[NY];           // PML profile along y
+  V S[NY * D::PITCH];
+  V twx[D::MX];                        // exp(-2 pi i j / MX)
+  V twn[D::NKX];                       // exp(-2 pi i k / NX), k <= MX (real-FFT split)
+  V twy[NY];                           // exp(-2 pi i j / NY)
+  V mul[NY > D::NKX ? NY : D::NKX];    // optional derivative factor by kx or by ky_pos
+  float px[NX];                        // PML profile along x of the component handled
+  float py[NY];                        // PML profile along y
 };
 
-// Copy the slab twiddles and up to two PML profiles into LDS (caller syncs).
+// Tables into LDS (caller syncs). mult_mode: 0 none, 1 per kx (NKX entries),
+// 2 per ky_pos (NY entries).
 template <int NX, int NY, int NZ, typename V>
 __device__ __forceinline__ void load_slab_tables(SlabLds<NX, NY, NZ, V>& L, const WaveTables& t,
-                                                 const float* pml_x, const float* pml_y, int tid) {
+                                                 const float* pml_x, const float* pml_y, const V* mult,
+                                                 int mult_mode, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
+  constexpr int NT = kThreadsSlab;
   const auto& T = TabSel<V>::get(t);
-  for (int i = tid; i < D::TWN; i += NT) {
-    V w;
-    if (i < D::MX) w = T.tw_mx[i];
-    else if (i < D::MX + D::NKX) w = T.tw_nx[i - D::MX];
-    else w = T.tw_y[i - D::MX - D::NKX];
-    L.tw[i] = w;
-  }
+  for (int i = tid; i < D::MX; i += NT) L.twx[i] = T.tw_mx[i];
+  for (int i = tid; i < D::NKX; i += NT) L.twn[i] = T.tw_nx[i];
+  for (int i = tid; i < NY; i += NT) L.twy[i] = T.tw_y[i];
+  if (mult_mode == 1)
+    for (int i = tid; i < D::NKX; i += NT) L.mul[i] = mult[i];
+  else if (mult_mode == 2)
+    for (int i = tid; i < NY; i += NT) L.mul[i] = mult[i];
   if (pml_x)
     for (int i = tid; i < NX; i += NT) L.px[i] = pml_x[i];
   if (pml_y)
     for (int i = tid; i < NY; i += NT) L.py[i] = pml_y[i];
 }
 
+// Real-space register layout shared by every slab kernel: loop slot i of a
+// thread is item b = tid + i * kThreadsSlab (valid while b < NX0), the row
+// y = b / MXB and offset n1 = b % MXB; value m (< RX0) is the packed pair
+// n = n1 + MXB m of row y, i.e. x = 2n, 2n + 1, at float2 index y * MX + n of
+// the slab.
+template <int NX, int NY, int NZ>
+struct RowItem {
+  using D = Dims<NX, NY, NZ>;
+  int y, n1;
+  bool ok;
+  __device__ __forceinline__ RowItem(int tid, int i) {
+    const int b = tid + i * kThreadsSlab;
+    ok = b < D::NX0;
+    y = b / D::MXB;
+    n1 = b % D::MXB;
+  }
+  __device__ __forceinline__ int pair(int m) const { return y * D::MX + n1 + D::MXB * m; }
+  __device__ __forceinline__ int n(int m) const { return n1 + D::MXB * m; }
+};
+
+// Load one real slab (float2 pairs) in the register layout.
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void load_real(RealRegs<NX, NY, NZ>& r,
+                                          const float2* __restrict__ src, int tid) {
+  using D = Dims<NX, NY, NZ>;
+#pragma unroll
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) r[i][m] = src[it.pair(m)];
+    }
+  }
+}
+
 // ---- slab transforms -------------------------------------------------------
 
-// R2C post-processing of rows already transformed by a forward MX-point FFT:
-// row y holds Z[k] (Z = FFT of x[2n] + i x[2n+1]) at digit-reversed positions;
-// on exit it holds X[k], k = 0..MX, in natural order (X = real FFT of x).
-// Rows are processed in chunks of RC: read all pairs of the chunk, barrier, write.
+// y inverse transform of the slab spectrum g[kx][ky_pos] (times an optional
+// derivative factor L.mul by kx (mode 1) or ky_pos (mode 2)), read straight
+// from HBM into the stage-1 butterflies; leaves S[y][kx] in natural y order.
+// Caller syncs before (tables); ends synced.
 template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void r2c_post(V* S, const V* tw_nx, int tid) {
+__device__ __forceinline__ void y_inverse_from_global(SlabLds<NX, NY, NZ, V>& L, const float2* __restrict__ g,
+                                                      int mode, int tid) {
   using D = Dims<NX, NY, NZ>;
+  constexpr int NT = kThreadsSlab, M = D::MYB, R0 = D::RY0;
+  float2 r[D::IY1][M];
+#pragma unroll
+  for (int i = 0; i < D::IY1; ++i) {   // every global load in flight before any arithmetic
+    const int b = tid + i * NT;
+    if (b < D::NY1) {
+      const int kx = b % D::NKX, mb = b / D::NKX;
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) r[i][k1] = g[kx * NY + M * mb + k1];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D::IY1; ++i) {
+    const int b = tid + i * NT;
+    if (b < D::NY1) {
+      const int kx = b % D::NKX, mb = b / D::NKX;
+      V a[M];
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) {
+        a[k1] = widen<V>(r[i][k1]);
+        if (mode == 1) a[k1] = cmul(a[k1], L.mul[kx]);
+        else if (mode == 2) a[k1] = cmul(a[k1], L.mul[M * mb + k1]);
+      }
+      dft_r<M, true>(a);
+#pragma unroll
+      for (int n1 = 0; n1 < M; ++n1) L.S[(M * mb + n1) * D::PITCH + kx] = a[n1];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < D::IY0; ++i) {
+    const int b = tid + i * NT;
+    if (b < D::NY0) {
+      const int kx = b % D::NKX, n1 = b / D::NKX;
+      V a[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) a[m] = L.S[(n1 + M * m) * D::PITCH + kx];
+      if constexpr (M > 1) stage_twiddle<R0, true>(a, L.twy, n1);
+      dft_r<R0, true>(a);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) L.S[(n1 + M * m) * D::PITCH + kx] = a[m];
+    }
+  }
+  __syncthreads();
+}
+
+// y forward transform of S[y][kx] (natural y) into the slab spectrum g[kx][ky_pos]:
+// stage 0 in LDS, stage 1 straight from registers to HBM. Caller syncs before.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void y_forward_to_global(SlabLds<NX, NY, NZ, V>& L, float2* __restrict__ g, int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int NT = kThreadsSlab, M = D::MYB, R0 = D::RY0;
+#pragma unroll
+  for (int i = 0; i < D::IY0; ++i) {
+    const int b = tid + i * NT;
+    if (b < D::NY0) {
+      const int kx = b % D::NKX, n1 = b / D::NKX;
+      V a[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) a[m] = L.S[(n1 + M * m) * D::PITCH + kx];
+      dft_r<R0, false>(a);
+      if constexpr (M > 1) stage_twiddle<R0, false>(a, L.twy, n1);
+#pragma unroll
+      for (int k = 0; k < R0; ++k) L.S[(n1 + M * k) * D::PITCH + kx] = a[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < D::IY1; ++i) {
+    const int b = tid + i * NT;
+    if (b < D::NY1) {
+      const int kx = b % D::NKX, mb = b / D::NKX;
+      V a[M];
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) a[k1] = L.S[(M * mb + k1) * D::PITCH + kx];
+      dft_r<M, false>(a);
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) g[kx * NY + M * mb + k1] = narrow(a[k1]);
+    }
+  }
+}
+
+// The x transform of a real row of NX values runs as an MX-point complex FFT
+// of the packed pairs z[n] = x[2n] + i x[2n+1] plus the split
+//   X[k] = E_k + w^k O_k,  E_k = (Z[k] + conj Z[MX-k]) / 2,
+//   O_k = (Z[k] - conj Z[MX-k]) / (2i),  w = exp(-2 pi i / NX),
+// (and its inverse before the inverse transform). Frequencies k and MX - k
+// meet in stage-1 blocks b and R0 - b (mod R0), so one thread takes both
+// blocks of a pair {g, R0 - g} (g = 1..R0/2-1) or {0, R0/2} (g = 0, which also
+// owns X[MX]) and the split runs in its registers.
+template <typename V>
+__device__ __forceinline__ V split_fwd(V zk, V zp, V w) {   // X[k] from Z[k], Z[MX-k]
   using Sc = typename ScalarOf<V>::T;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int MX = D::MX, NP = D::NP, TOTAL = D::RC * NP;
-  constexpr int IT = (TOTAL + NT - 1) / NT;
+  const V e = cscale(cadd(zk, cconj(zp)), (Sc)0.5);
+  const V d = csub(zk, cconj(zp));
+  const V o = mkc<V>((Sc)0.5 * d.y, (Sc)-0.5 * d.x);
+  return cadd(e, cmul(w, o));
+}
+template <typename V>
+__device__ __forceinline__ V split_inv(V xk, V xp, V w) {   // 2 Z[k] from X[k], X[MX-k]
+  const V s = cadd(xk, cconj(xp)), d = csub(xk, cconj(xp));
+  const V wd = cmulconj(d, w);
+  return mkc<V>(s.x - wd.y, s.y + wd.x);
+}
+
+// Twiddles w^(b + R0 k1), k1 = 0, 1, ..., from the table exp(-2 pi i k / NX),
+// k <= MX: FP64 steps by w^R0 (one multiply per value), FP32 reads each.
+template <int R0, typename V>
+struct SplitTwiddle {
+  const V* twn;
+  int b;
+  V cur, step;
+  __device__ __forceinline__ SplitTwiddle(const V* t, int b_) : twn(t), b(b_) {
+    if constexpr (std::is_same<V, double2>::value) {
+      cur = twn[b];
+      step = twn[R0];
+    }
+  }
+  // value for k1; must be called with k1 = 0, 1, 2, ... in order
+  __device__ __forceinline__ V at(int k1) {
+    if constexpr (std::is_same<V, double2>::value) {
+      if (k1 > 0) cur = cmul(cur, step);
+      return cur;
+    } else {
+      return twn[b + R0 * k1];
+    }
+  }
+};
+
+template <int NX, int NY, int NZ>
+struct PairItem {
+  using D = Dims<NX, NY, NZ>;
+  int y, g, ma, mb;
+  bool ok;
+  __device__ __forceinline__ PairItem(int tid, int i) {
+    const int b = tid + i * kThreadsSlab;
+    ok = b < D::NXP;
+    y = b % NY;
+    g = b / NY;
+    ma = g;
+    mb = g == 0 ? D::RX0 / 2 : D::RX0 - g;
+  }
+};
+
+// Rows S[y][kx] (natural kx, X[0..MX]) -> inverse x transform -> packed real
+// pairs in the register layout (unnormalised). Caller syncs before.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L,
+                                                  RealRegs<NX, NY, NZ>& out,
+                                                  int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX;
+  V za[D::IXP][M], zb[D::IXP][M];
 #pragma unroll
-  for (int r0 = 0; r0 < NY; r0 += D::RC) {
-    V o1[IT], o2[IT];
+  for (int i = 0; i < D::IXP; ++i) {
+    const PairItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      const V* row = L.S + it.y * D::PITCH;
+      V xa[M], xb[M];
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (w < TOTAL) {
-        const int y = r0 + w / NP, k = w % NP;
-        const V* row = S + y * D::PITCH;
-        if (k == 0) {
-          const V z0 = row[0];
-          o1[i] = mkc<V>(z0.x + z0.y, (Sc)0);
-          o2[i] = mkc<V>(z0.x - z0.y, (Sc)0);
-        } else {
-          const V A = row[fft_pos(MX, k)];
-          const V B = cconj(row[fft_pos(MX, MX - k)]);
-          const V E = cscale(cadd(A, B), (Sc)0.5);
-          const V Dd = csub(A, B);
-          const V O = mkc<V>((Sc)0.5 * Dd.y, (Sc)-0.5 * Dd.x);   // (A - B) / (2i)
-          const V WO = cmul(tw_nx[k], O);
-          o1[i] = cadd(E, WO);
-          o2[i] = cconj(csub(E, WO));
+      for (int k1 = 0; k1 < M; ++k1) {
+        xa[k1] = row[it.ma + R0 * k1];
+        xb[k1] = row[it.mb + R0 * k1];
+      }
+      const V xm = row[MX];
+      SplitTwiddle<R0, V> wa(L.twn, it.ma), wb(L.twn, it.mb);
+      // (branches rather than selects keep xa, xb in registers)
+      if (it.g != 0) {
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          za[i][k1] = split_inv(xa[k1], xb[M - 1 - k1], wa.at(k1));
+          zb[i][k1] = split_inv(xb[k1], xa[M - 1 - k1], wb.at(k1));
+        }
+      } else {
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          za[i][k1] = split_inv(xa[k1], k1 == 0 ? xm : xa[(M - k1) % M], wa.at(k1));
+          zb[i][k1] = split_inv(xb[k1], xb[M - 1 - k1], wb.at(k1));
         }
       }
+      dft_r<M, true>(za[i]);
+      dft_r<M, true>(zb[i]);
     }
-    __syncthreads();
+  }
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (w < TOTAL) {
-        const int y = r0 + w / NP, k = w % NP;
-        V* row = S + y * D::PITCH;
-        row[k] = o1[i];
-        row[MX - k] = o2[i];   // k == 0 writes X[MX]; k == MX/2 rewrites the same value
+  for (int i = 0; i < D::IXP; ++i) {
+    const PairItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      V* row = L.S + it.y * D::PITCH;
+#pragma unroll
+      for (int n1 = 0; n1 < M; ++n1) {
+        row[M * it.ma + n1] = za[i][n1];
+        row[M * it.mb + n1] = zb[i][n1];
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      const V* row = L.S + it.y * D::PITCH;
+      V a[R0];
+#pragma unroll
+      for (int k = 0; k < R0; ++k) a[k] = row[it.n1 + M * k];
+      if constexpr (M > 1) stage_twiddle<R0, true>(a, L.twx, it.n1);
+      dft_r<R0, true>(a);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) out[i][m] = narrow(a[m]);
+    }
   }
 }
 
-// C2R pre-processing: row y holds X[k], k = 0..MX natural; on exit it holds
-// Z'[k] = (X[k] + conj X[MX-k]) + i exp(+2 pi i k/NX) (X[k] - conj X[MX-k]) at
-// digit-reversed positions, so that an inverse MX-point FFT yields
-// x[2n] + i x[2n+1] (unnormalised real inverse transform).
+// Packed real pairs in the register layout -> forward x transform -> rows
+// S[y][kx] (natural kx, X[0..MX]). The first stage writes the LDS slots the
+// same thread read in x_inverse_to_regs, so no barrier is needed before it.
 template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void c2r_pre(V* S, const V* tw_nx, int tid) {
+__device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L,
+                                                    const RealRegs<NX, NY, NZ>& in,
+                                                    int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int MX = D::MX, NP = D::NP, TOTAL = D::RC * NP;
-  constexpr int IT = (TOTAL + NT - 1) / NT;
+  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX;
 #pragma unroll
-  for (int r0 = 0; r0 < NY; r0 += D::RC) {
-    V o1[IT], o2[IT];
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      V* row = L.S + it.y * D::PITCH;
+      V a[R0];
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (w < TOTAL) {
-        const int y = r0 + w / NP, k = w % NP;
-        const V* row = S + y * D::PITCH;
-        const V Xk = row[k], Xm = row[MX - k];
-        {
-          const V s = cadd(Xk, cconj(Xm)), d = csub(Xk, cconj(Xm));
-          const V wd = cmulconj(d, tw_nx[k]);
-          o1[i] = mkc<V>(s.x - wd.y, s.y + wd.x);
+      for (int m = 0; m < R0; ++m) a[m] = widen<V>(in[i][m]);
+      dft_r<R0, false>(a);
+      if constexpr (M > 1) stage_twiddle<R0, false>(a, L.twx, it.n1);
+#pragma unroll
+      for (int k = 0; k < R0; ++k) row[it.n1 + M * k] = a[k];
+    }
+  }
+  __syncthreads();
+  V xa[D::IXP][M], xb[D::IXP][M], xm[D::IXP];
+#pragma unroll
+  for (int i = 0; i < D::IXP; ++i) {
+    const PairItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      const V* row = L.S + it.y * D::PITCH;
+      V za[M], zb[M];
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) {
+        za[k1] = row[M * it.ma + k1];
+        zb[k1] = row[M * it.mb + k1];
+      }
+      dft_r<M, false>(za);
+      dft_r<M, false>(zb);
+      SplitTwiddle<R0, V> wa(L.twn, it.ma), wb(L.twn, it.mb);
+      // partner Z[MX - k]; for k = 0 it is Z[MX] = Z[0]
+      if (it.g != 0) {
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          xa[i][k1] = split_fwd(za[k1], zb[M - 1 - k1], wa.at(k1));
+          xb[i][k1] = split_fwd(zb[k1], za[M - 1 - k1], wb.at(k1));
         }
-        {
-          const V s = cadd(Xm, cconj(Xk)), d = csub(Xm, cconj(Xk));
-          const V wd = cmulconj(d, tw_nx[MX - k]);
-          o2[i] = mkc<V>(s.x - wd.y, s.y + wd.x);
+      } else {
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          xa[i][k1] = split_fwd(za[k1], za[(M - k1) % M], wa.at(k1));
+          xb[i][k1] = split_fwd(zb[k1], zb[M - 1 - k1], wb.at(k1));
         }
       }
+      xm[i] = mkc<V>(za[0].x - za[0].y, (typename ScalarOf<V>::T)0);
     }
-    __syncthreads();
+  }
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (w < TOTAL) {
-        const int y = r0 + w / NP, k = w % NP;
-        V* row = S + y * D::PITCH;
-        row[fft_pos(MX, k)] = o1[i];
-        if (k != 0 && 2 * k != MX) row[fft_pos(MX, MX - k)] = o2[i];
+  for (int i = 0; i < D::IXP; ++i) {
+    const PairItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+      V* row = L.S + it.y * D::PITCH;
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) {
+        row[it.ma + R0 * k1] = xa[i][k1];
+        row[it.mb + R0 * k1] = xb[i][k1];
       }
-    }
-    __syncthreads();
-  }
-}
-
-// Real slab (packed pairs at S[y*PITCH + n]) -> slab spectrum (kx natural,
-// ky digit-reversed) in place. Caller syncs before.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void slab_r2c(SlabLds<NX, NY, NZ, V>& L, int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  fft_forward<D::MX, false, NY, D::PITCH, 1, NT>(L.S, L.tw, tid);
-  r2c_post<NX, NY, NZ>(L.S, L.tw + D::MX, tid);
-  fft_forward<NY, true, D::NKX, 1, D::PITCH, NT>(L.S, L.tw + D::MX + D::NKX, tid);
-}
-
-// Slab spectrum -> real slab (packed pairs), unnormalised. Caller syncs before.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void slab_c2r(SlabLds<NX, NY, NZ, V>& L, int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  fft_inverse<NY, true, D::NKX, 1, D::PITCH, NT>(L.S, L.tw + D::MX + D::NKX, tid);
-  c2r_pre<NX, NY, NZ>(L.S, L.tw + D::MX, tid);
-  fft_inverse<D::MX, false, NY, D::PITCH, 1, NT>(L.S, L.tw, tid);
-}
-
-// Global slab spectrum [kx][ky_pos] -> LDS [ky_pos][kx], times mult (0: none,
-// 1: per-kx table, 2: per-ky_pos table; mult is global and read in the same
-// batch as the data).
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void load_spec(V* S, const float2* __restrict__ g, int mode,
-                                          const V* __restrict__ mult, int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int IT = (D::SLAB_C + NT - 1) / NT;
-  float2 r[IT];
-  V m[IT];
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {     // all global loads in flight before any LDS write
-    const int e = tid + i * NT;
-    if (e < D::SLAB_C) {
-      r[i] = g[e];
-      if (mode == 1) m[i] = mult[e / NY];
-      else if (mode == 2) m[i] = mult[e % NY];
+      if (it.g == 0) row[MX] = xm[i];
     }
   }
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_C) {
-      const int kx = e / NY, p = e % NY;
-      V v = widen<V>(r[i]);
-      if (mode != 0) v = cmul(v, m[i]);
-      S[p * D::PITCH + kx] = v;
-    }
-  }
+  __syncthreads();
 }
 
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void store_spec(const V* S, float2* __restrict__ g, int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int IT = (D::SLAB_C + NT - 1) / NT;
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_C) {
-      const int kx = e / NY, p = e % NY;
-      g[e] = narrow(S[p * D::PITCH + kx]);
-    }
-  }
-}
-
-// Batched read of a z-pencil tile (fixed kx, TY consecutive ky_pos, all z) into
-// LDS columns [col0, col0 + TY) of a row pitch W.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void load_tile(V* T, int W, int col0, const float2* __restrict__ H, int kx, int p0,
-                                          int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int TY = D::TY;
-  float2 r[D::ZIT];
-#pragma unroll
-  for (int i = 0; i < D::ZIT; ++i) {
-    const int e = tid + i * kThreadsZ;
-    if (e < NZ * TY) r[i] = H[((size_t)(e / TY) * D::NKX + kx) * NY + p0 + e % TY];
-  }
-#pragma unroll
-  for (int i = 0; i < D::ZIT; ++i) {
-    const int e = tid + i * kThreadsZ;
-    if (e < NZ * TY) T[(e / TY) * W + col0 + e % TY] = widen<V>(r[i]);
-  }
-}
-
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void store_tile(const V* T, int W, int col0, float2* __restrict__ H, int kx, int p0,
-                                           int tid) {
-  using D = Dims<NX, NY, NZ>;
-  constexpr int TY = D::TY;
-#pragma unroll
-  for (int i = 0; i < D::ZIT; ++i) {
-    const int e = tid + i * kThreadsZ;
-    if (e < NZ * TY) H[((size_t)(e / TY) * D::NKX + kx) * NY + p0 + e % TY] = narrow(T[(e / TY) * W + col0 + e % TY]);
-  }
-}
-
-// ---- LDS workspace of a pencil workgroup ---------------------------------------
-// Per-tile spectral tables: the z twiddles, the sinc arguments along z and y,
-// and the derivative factor of the multiplier along z (by kz_pos) or y (by
-// ky_pos); the x factor is one value per tile.
-template <int NX, int NY, int NZ, typename V, int W>
+// ---- z pencils ---------------------------------------------------------------
+// A tile is TY consecutive ky_pos columns (p0..p0+TY-1) of one kx over all z,
+// held in LDS as T[z_index * TY + col]. Per-tile tables: the z twiddles, the
+// sinc arguments along z and y, and the derivative factor along z (by kz_pos)
+// or y (by ky_pos); the x factor is one value per tile.
+template <int NX, int NY, int NZ, typename V, int NB>
 struct PencilLds {
   using Sc = typename ScalarOf<V>::T;
-  V T[NZ * W];
+  using D = Dims<NX, NY, NZ>;
+  V T[NB][NZ * D::TY];
   V twz[NZ];
   Sc hz[NZ];
   V mz[NZ];
-  Sc hy[16];
-  V my[16];
+  Sc hy[D::TY];
+  V my[D::TY];
 };
 
-// Load the tile's tables; caller syncs. mz / my may be null when unused.
-template <int NX, int NY, int NZ, typename V, int W>
-__device__ __forceinline__ void load_pencil_tables(PencilLds<NX, NY, NZ, V, W>& L, const WaveTables& t, int p0,
-                                                   const V* mz, const V* my, int tid) {
+// Load the tile's tables; caller syncs. The derivative factor of a pass is kept
+// separable, m = my[col] * mz[q]: my = mx (one value per tile) times the y
+// factor (if any) by column, mz the z factor (if any) by kz position; absent
+// factors are 1, so a product with them is exact.
+template <int NX, int NY, int NZ, typename V, int NB>
+__device__ __forceinline__ void load_pencil_tables(PencilLds<NX, NY, NZ, V, NB>& L, const WaveTables& t, int p0,
+                                                   V mx, const V* my, const V* mz, int tid) {
   using D = Dims<NX, NY, NZ>;
+  using Sc = typename ScalarOf<V>::T;
   const auto& T = TabSel<V>::get(t);
   for (int i = tid; i < NZ; i += kThreadsZ) {
     L.twz[i] = T.tw_z[i];
     L.hz[i] = T.hz[i];
-    if (mz) L.mz[i] = mz[i];
+  }
+  if (mz) {
+    for (int i = tid; i < NZ; i += kThreadsZ) L.mz[i] = mz[i];
+  } else {
+    for (int i = tid; i < NZ; i += kThreadsZ) L.mz[i] = mkc<V>((Sc)1, (Sc)0);
   }
   if (tid < D::TY) {
     L.hy[tid] = T.hy[p0 + tid];
-    if (my) L.my[tid] = my[p0 + tid];
+    if (my) L.my[tid] = cmul(mx, my[p0 + tid]);
+    else L.my[tid] = mx;
   }
+}
+
+// Global loads of a tile in the stage-0 butterfly layout: slot i of a thread is
+// item b = tid + i * kThreadsZ, column b % TY, offset n1 = b / TY; value m is z = n1 + MZB m.
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void z_load(ZRegs<NX, NY, NZ>& r,
+                                       const float2* __restrict__ H, int kx, int p0, int tid) {
+  using D = Dims<NX, NY, NZ>;
+#pragma unroll
+  for (int i = 0; i < D::IZ0; ++i) {
+    const int b = tid + i * kThreadsZ;
+    if (b < D::NZ0) {
+      const int col = b % D::TY, n1 = b / D::TY;
+#pragma unroll
+      for (int m = 0; m < D::RZ0; ++m) r[i][m] = H[((size_t)(n1 + D::MZB * m) * D::NKX + kx) * NY + p0 + col];
+    }
+  }
+}
+
+// Forward stage 0 of the loaded tile into T.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void z_fwd0(V* T, const ZRegs<NX, NY, NZ>& r,
+                                       const V* twz, int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int R0 = D::RZ0, M = D::MZB;
+#pragma unroll
+  for (int i = 0; i < D::IZ0; ++i) {
+    const int b = tid + i * kThreadsZ;
+    if (b < D::NZ0) {
+      const int col = b % D::TY, n1 = b / D::TY;
+      V a[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) a[m] = widen<V>(r[i][m]);
+      dft_r<R0, false>(a);
+      if constexpr (M > 1) stage_twiddle<R0, false>(a, twz, n1);
+#pragma unroll
+      for (int k = 0; k < R0; ++k) T[(n1 + M * k) * D::TY + col] = a[k];
+    }
+  }
+}
+
+// Forward stage 1 from T into registers: slot i is item b = tid + i * kThreadsZ,
+// column b % TY, block mb = b / TY; value k1 is at kz position MZB mb + k1.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void z_fwd1(const V* T, ZVals<NX, NY, NZ, V>& v, int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int M = D::MZB;
+#pragma unroll
+  for (int i = 0; i < D::IZ1; ++i) {
+    const int b = tid + i * kThreadsZ;
+    if (b < D::NZ1) {
+      const int col = b % D::TY, mb = b / D::TY;
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) v[i][k1] = T[(M * mb + k1) * D::TY + col];
+      dft_r<M, false>(v[i]);
+    }
+  }
+}
+
+// Inverse stage 1 of register values back into T (the slots z_fwd1 read).
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void z_inv1(V* T, ZVals<NX, NY, NZ, V>& v, int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int M = D::MZB;
+#pragma unroll
+  for (int i = 0; i < D::IZ1; ++i) {
+    const int b = tid + i * kThreadsZ;
+    if (b < D::NZ1) {
+      const int col = b % D::TY, mb = b / D::TY;
+      dft_r<M, true>(v[i]);
+#pragma unroll
+      for (int n1 = 0; n1 < M; ++n1) T[(M * mb + n1) * D::TY + col] = v[i][n1];
+    }
+  }
+}
+
+// Inverse stage 0 from T straight to HBM.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void z_inv0_store(const V* T, float2* __restrict__ H, int kx, int p0, const V* twz,
+                                             int tid) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int R0 = D::RZ0, M = D::MZB;
+#pragma unroll
+  for (int i = 0; i < D::IZ0; ++i) {
+    const int b = tid + i * kThreadsZ;
+    if (b < D::NZ0) {
+      const int col = b % D::TY, n1 = b / D::TY;
+      V a[R0];
+#pragma unroll
+      for (int k = 0; k < R0; ++k) a[k] = T[(n1 + M * k) * D::TY + col];
+      if constexpr (M > 1) stage_twiddle<R0, true>(a, twz, n1);
+      dft_r<R0, true>(a);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) H[((size_t)(n1 + M * m) * D::NKX + kx) * NY + p0 + col] = narrow(a[m]);
+    }
+  }
+}
+
+// kappa / N at column col, kz position q of the tile.
+template <typename Sc>
+__device__ __forceinline__ Sc kappa_n(Sc hx, Sc hy, Sc hz, float inv_ntot) {
+  return sinc_of_sq(hx * hx + hy * hy + hz * hz) * (Sc)inv_ntot;
 }
 
 // blockIdx -> (slab z, component xi) so the three components of one slab run on
@@ -368,35 +642,32 @@ __device__ __forceinline__ void slab_field_of_block(int b, int& z, int& xi) {
 
 // rho_xi = p0 / (3 c0^2); plane 0 = p0[z = 0]; spec0 = slab R2C of p0.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_init(const float* __restrict__ p0, WaveBuffers B,
-                                                                    float* __restrict__ plane0, WaveTables t,
-                                                                    WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restrict__ p0, WaveBuffers B,
+                                                           float* __restrict__ plane0, WaveTables t,
+                                                           WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t off = (size_t)z * D::SLAB_P;
-  const float2* src = reinterpret_cast<const float2*>(p0) + off;
-  load_slab_tables(L, t, nullptr, nullptr, tid);
-  float2 v[EPT];
+  load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
+  float2 v[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(v, reinterpret_cast<const float2*>(p0) + off, tid);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i)
-    if (tid + i * NT < D::SLAB_P) v[i] = src[tid + i * NT];
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      L.S[(e / D::MX) * D::PITCH + e % D::MX] = widen<V>(v[i]);
-      const float2 r = make_float2(v[i].x * sc.inv_3c2, v[i].y * sc.inv_3c2);
+      for (int m = 0; m < D::RX0; ++m) {
+        const float2 r = make_float2(v[i][m].x * sc.inv_3c2, v[i][m].y * sc.inv_3c2);
 #pragma unroll
-      for (int xi = 0; xi < 3; ++xi) reinterpret_cast<float2*>(B.rho[xi])[off + e] = r;
-      if (z == 0) reinterpret_cast<float2*>(plane0)[e] = v[i];
+        for (int xi = 0; xi < 3; ++xi) reinterpret_cast<float2*>(B.rho[xi])[off + it.pair(m)] = r;
+        if (z == 0) reinterpret_cast<float2*>(plane0)[it.pair(m)] = v[i][m];
+      }
     }
   }
   __syncthreads();
-  slab_r2c(L, tid);
-  store_spec<NX, NY, NZ>(L.S, B.spec[0] + (size_t)z * D::SLAB_C, tid);
+  x_forward_from_regs(L, v, tid);
+  y_forward_to_global(L, B.spec[0] + (size_t)z * D::SLAB_C, tid);
 }
 
 // Pencil pass of the gradient: in = FFT_xy(p) (overwritten by Q), out2 = Gz, with
@@ -408,31 +679,37 @@ __global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, flo
                                                      WaveTables t, float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
-  constexpr int TY = D::TY, W = 2 * TY;
-  __shared__ PencilLds<NX, NY, NZ, V, W> L;
+  __shared__ PencilLds<NX, NY, NZ, V, 2> L;
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
-  const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  load_pencil_tables(L, t, p0, tab.mpz, (const V*)nullptr, tid);
+  const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
+  float2 r[D::IZ0][D::RZ0];
+  z_load<NX, NY, NZ>(r, P, kx, p0, tid);
+  load_pencil_tables(L, t, p0, mkc<V>((Sc)1, (Sc)0), (const V*)nullptr, tab.mpz, tid);
   const Sc hx = tab.hx[kx];
-  load_tile<NX, NY, NZ>(L.T, W, 0, P, kx, p0, tid);
   __syncthreads();
-  fft_forward<NZ, true, TY, 1, W, kThreadsZ>(L.T, L.twz, tid);
+  z_fwd0<NX, NY, NZ>(L.T[0], r, L.twz, tid);
+  __syncthreads();
+  V v[D::IZ1][D::MZB], w[D::IZ1][D::MZB];
+  z_fwd1<NX, NY, NZ>(L.T[0], v, tid);
 #pragma unroll
-  for (int i = 0; i < D::ZIT; ++i) {
-    const int e = tid + i * kThreadsZ;
-    if (e < NZ * TY) {
-      const int q = e / TY, j = e % TY;
-      const Sc kap = sinc_of_sq(hx * hx + L.hy[j] * L.hy[j] + L.hz[q] * L.hz[q]) * (Sc)inv_ntot;
-      const V v = cscale(L.T[q * W + j], kap);
-      L.T[q * W + j] = v;
-      L.T[q * W + TY + j] = cmul(v, L.mz[q]);
+  for (int i = 0; i < D::IZ1; ++i) {
+    const int b = tid + i * kThreadsZ;
+    const int col = b % D::TY, mb = b / D::TY;
+#pragma unroll
+    for (int k1 = 0; k1 < D::MZB; ++k1) {
+      const int q = D::MZB * mb + k1;
+      if (b < D::NZ1) {
+        v[i][k1] = cscale(v[i][k1], kappa_n(hx, L.hy[col], L.hz[q], inv_ntot));
+        w[i][k1] = cmul(v[i][k1], L.mz[q]);
+      }
     }
   }
+  z_inv1<NX, NY, NZ>(L.T[0], v, tid);
+  z_inv1<NX, NY, NZ>(L.T[1], w, tid);
   __syncthreads();
-  fft_inverse<NZ, true, W, 1, W, kThreadsZ>(L.T, L.twz, tid);
-  store_tile<NX, NY, NZ>(L.T, W, 0, P, kx, p0, tid);
-  store_tile<NX, NY, NZ>(L.T, W, TY, Gz, kx, p0, tid);
+  z_inv0_store<NX, NY, NZ>(L.T[0], P, kx, p0, L.twz, tid);
+  z_inv0_store<NX, NY, NZ>(L.T[1], Gz, kx, p0, L.twz, tid);
 }
 
 // Pencil pass applying kappa/N times i k_xi exp(s i k_xi dx/2) (PLUS: s = +1,
@@ -442,160 +719,164 @@ __global__ __launch_bounds__(kThreadsZ) void k_zmul(float2* H0, float2* H1, floa
                                                     float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
-  constexpr int TY = D::TY;
-  __shared__ PencilLds<NX, NY, NZ, V, TY> L;
+  __shared__ PencilLds<NX, NY, NZ, V, 1> L;
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x, xi = blockIdx.y;
   float2* H = xi == 0 ? H0 : (xi == 1 ? H1 : H2);
-  const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  load_pencil_tables(L, t, p0, xi == 2 ? (PLUS ? tab.mpz : tab.mmz) : (const V*)nullptr,
-                     xi == 1 ? (PLUS ? tab.mpy : tab.mmy) : (const V*)nullptr, tid);
+  const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
+  float2 r[D::IZ0][D::RZ0];
+  z_load<NX, NY, NZ>(r, H, kx, p0, tid);
+  load_pencil_tables(L, t, p0, xi == 0 ? (PLUS ? tab.mpx : tab.mmx)[kx] : mkc<V>((Sc)1, (Sc)0),
+                     xi == 1 ? (PLUS ? tab.mpy : tab.mmy) : (const V*)nullptr,
+                     xi == 2 ? (PLUS ? tab.mpz : tab.mmz) : (const V*)nullptr, tid);
   const Sc hx = tab.hx[kx];
-  const V mxk = (PLUS ? tab.mpx : tab.mmx)[kx];
-  load_tile<NX, NY, NZ>(L.T, TY, 0, H, kx, p0, tid);
   __syncthreads();
-  fft_forward<NZ, true, TY, 1, TY, kThreadsZ>(L.T, L.twz, tid);
+  z_fwd0<NX, NY, NZ>(L.T[0], r, L.twz, tid);
+  __syncthreads();
+  V v[D::IZ1][D::MZB];
+  z_fwd1<NX, NY, NZ>(L.T[0], v, tid);
 #pragma unroll
-  for (int i = 0; i < D::ZIT; ++i) {
-    const int e = tid + i * kThreadsZ;
-    if (e < NZ * TY) {
-      const int q = e / TY, j = e % TY;
-      const Sc kap = sinc_of_sq(hx * hx + L.hy[j] * L.hy[j] + L.hz[q] * L.hz[q]) * (Sc)inv_ntot;
-      const V m = xi == 0 ? mxk : (xi == 1 ? L.my[j] : L.mz[q]);
-      L.T[e] = cmul(cscale(L.T[e], kap), m);
+  for (int i = 0; i < D::IZ1; ++i) {
+    const int b = tid + i * kThreadsZ;
+    const int col = b % D::TY, mb = b / D::TY;
+#pragma unroll
+    for (int k1 = 0; k1 < D::MZB; ++k1) {
+      const int q = D::MZB * mb + k1;
+      if (b < D::NZ1) {
+        v[i][k1] = cmul(cscale(v[i][k1], kappa_n(hx, L.hy[col], L.hz[q], inv_ntot)), cmul(L.my[col], L.mz[q]));
+      }
     }
   }
+  z_inv1<NX, NY, NZ>(L.T[0], v, tid);
   __syncthreads();
-  fft_inverse<NZ, true, TY, 1, TY, kThreadsZ>(L.T, L.twz, tid);
-  store_tile<NX, NY, NZ>(L.T, TY, 0, H, kx, p0, tid);
+  z_inv0_store<NX, NY, NZ>(L.T[0], H, kx, p0, L.twz, tid);
 }
 
 // Velocity update of component xi for slab z, then R2C of the new u_xi.
 // Q, Gz: outputs of k_zgrad; U0, U1, U2: spectra of the new u components
 // (U2 aliases Gz: only this block reads Gz[z] and it does so before writing).
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_u(const float2* __restrict__ Q, const float2* Gz,
-                                                                 float2* U0, float2* U1, float2* U2, WaveBuffers B,
-                                                                 WaveTables t, WaveScalars sc, int init) {
+__global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict__ Q, const float2* Gz,
+                                                        float2* U0, float2* U1, float2* U2, WaveBuffers B,
+                                                        WaveTables t, WaveScalars sc, int init) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   int z, xi;
   slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
-  load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, tid);
-  if (xi == 0) load_spec<NX, NY, NZ>(L.S, Q + cz, 1, tab.mpx, tid);
-  else if (xi == 1) load_spec<NX, NY, NZ>(L.S, Q + cz, 2, tab.mpy, tid);
-  else load_spec<NX, NY, NZ>(L.S, Gz + cz, 0, (const V*)nullptr, tid);
-  // prefetch the velocity component: its loads overlap the transform
   float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
-  float2 uo[EPT];
-  if (!init) {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i)
-      if (tid + i * NT < D::SLAB_P) uo[i] = u[tid + i * NT];
-  }
+  float2 uo[D::IX0][D::RX0];
+  if (!init) load_real<NX, NY, NZ>(uo, u, tid);   // in flight during the transform
+  load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr,
+                   xi == 0 ? tab.mpx : (xi == 1 ? tab.mpy : (const V*)nullptr), xi == 2 ? 0 : xi + 1, tid);
   const float azz = t.az[z];
   __syncthreads();
-  slab_c2r(L, tid);
+  y_inverse_from_global(L, (xi == 2 ? Gz : Q) + cz, xi == 2 ? 0 : xi + 1, tid);
+  float2 g[D::IX0][D::RX0];
+  x_inverse_to_regs(L, g, tid);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const int y = e / D::MX, n = e % D::MX;
-      const float2 g = narrow(L.S[y * D::PITCH + n]);
-      float a0, a1;
-      if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
-      else if (xi == 1) { a0 = a1 = L.py[y]; }
-      else { a0 = a1 = azz; }
-      const float2 o = init ? make_float2(g.x * sc.half_dt_over_rho0, g.y * sc.half_dt_over_rho0) : uo[i];
-      const float2 un = make_float2(a0 * (a0 * o.x - sc.dt_over_rho0 * g.x),
-                                    a1 * (a1 * o.y - sc.dt_over_rho0 * g.y));
-      u[e] = un;
-      L.S[y * D::PITCH + n] = widen<V>(un);
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        const int n = it.n(m);
+        float a0, a1;
+        if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
+        else if (xi == 1) { a0 = a1 = L.py[it.y]; }
+        else { a0 = a1 = azz; }
+        const float2 gv = g[i][m];
+        const float2 o = init ? make_float2(gv.x * sc.half_dt_over_rho0, gv.y * sc.half_dt_over_rho0) : uo[i][m];
+        const float2 un = make_float2(a0 * (a0 * o.x - sc.dt_over_rho0 * gv.x),
+                                      a1 * (a1 * o.y - sc.dt_over_rho0 * gv.y));
+        u[it.pair(m)] = un;
+        g[i][m] = un;
+      }
     }
   }
-  __syncthreads();
-  slab_r2c(L, tid);
+  x_forward_from_regs(L, g, tid);
   float2* U = xi == 0 ? U0 : (xi == 1 ? U1 : U2);
-  store_spec<NX, NY, NZ>(L.S, U + cz, tid);
+  y_forward_to_global(L, U + cz, tid);
 }
 
 // Density update of all three components of slab z, p = c0^2 sum rho, sensor
-// plane, and R2C of p into Pout.
+// plane, and R2C of p into Pout. The sum is formed from the new components as
+// stored (each thread re-reads its own values), which keeps the three
+// transforms free of a live accumulator.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_fwd_rho(const float2* __restrict__ H0,
-                                                                   const float2* __restrict__ H1,
-                                                                   const float2* __restrict__ H2, WaveBuffers B,
-                                                                   float2* __restrict__ Pout,
-                                                                   float* __restrict__ plane, WaveTables t,
-                                                                   WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restrict__ H0,
+                                                          const float2* __restrict__ H1,
+                                                          const float2* __restrict__ H2, WaveBuffers B,
+                                                          float2* __restrict__ Pout,
+                                                          float* __restrict__ plane, WaveTables t,
+                                                          WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  load_slab_tables(L, t, t.bx, t.by, tid);
+  load_slab_tables(L, t, t.bx, t.by, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
-  float2 pacc[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) pacc[i] = make_float2(0.f, 0.f);
 #pragma unroll 1
   for (int xi = 0; xi < 3; ++xi) {
     const float2* H = xi == 0 ? H0 : (xi == 1 ? H1 : H2);
-    load_spec<NX, NY, NZ>(L.S, H + cz, 0, (const V*)nullptr, tid);
-    __syncthreads();
-    slab_c2r(L, tid);
     float2* r = reinterpret_cast<float2*>(B.rho[xi]) + rz;
-    float2 rold[EPT];
+    // an opaque copy of the thread index: the LDS and global addresses of the
+    // passes are recomputed per component instead of being kept live across the loop
+    int tl = tid;
+    asm volatile("" : "+v"(tl));
+    __syncthreads();   // tables (first pass) / previous pass done with S
+    y_inverse_from_global(L, H + cz, 0, tl);
+    float2 ro[D::IX0][D::RX0];
+    load_real<NX, NY, NZ>(ro, r, tl);   // in flight during the x pass
+    float2 h[D::IX0][D::RX0];
+    x_inverse_to_regs(L, h, tl);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i)
-      if (tid + i * NT < D::SLAB_P) rold[i] = r[tid + i * NT];
+    for (int i = 0; i < D::IX0; ++i) {
+      const RowItem<NX, NY, NZ> it(tl, i);
+      if (it.ok) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NT;
-      if (e < D::SLAB_P) {
-        const int y = e / D::MX, n = e % D::MX;
-        const float2 h = narrow(L.S[y * D::PITCH + n]);
-        float b0, b1;
-        if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
-        else if (xi == 1) { b0 = b1 = L.py[y]; }
-        else { b0 = b1 = bzz; }
-        const float2 ro = rold[i];
-        const float2 rn = make_float2(b0 * (b0 * ro.x - sc.dt_rho0 * h.x), b1 * (b1 * ro.y - sc.dt_rho0 * h.y));
-        r[e] = rn;
-        pacc[i] = make_float2(pacc[i].x + rn.x, pacc[i].y + rn.y);
+        for (int m = 0; m < D::RX0; ++m) {
+          const int n = it.n(m);
+          float b0, b1;
+          if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
+          else if (xi == 1) { b0 = b1 = L.py[it.y]; }
+          else { b0 = b1 = bzz; }
+          r[it.pair(m)] = make_float2(b0 * (b0 * ro[i][m].x - sc.dt_rho0 * h[i][m].x),
+                                      b1 * (b1 * ro[i][m].y - sc.dt_rho0 * h[i][m].y));
+        }
       }
     }
-    __syncthreads();
   }
+  float2 p[D::IX0][D::RX0], r1[D::IX0][D::RX0], r2[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(p, reinterpret_cast<const float2*>(B.rho[0]) + rz, tid);
+  load_real<NX, NY, NZ>(r1, reinterpret_cast<const float2*>(B.rho[1]) + rz, tid);
+  load_real<NX, NY, NZ>(r2, reinterpret_cast<const float2*>(B.rho[2]) + rz, tid);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const float2 p = make_float2(pacc[i].x * sc.c2, pacc[i].y * sc.c2);
-      L.S[(e / D::MX) * D::PITCH + e % D::MX] = widen<V>(p);
-      if (z == 0) reinterpret_cast<float2*>(plane)[e] = p;
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        p[i][m] = make_float2((p[i][m].x + r1[i][m].x + r2[i][m].x) * sc.c2,
+                              (p[i][m].y + r1[i][m].y + r2[i][m].y) * sc.c2);
+        if (z == 0) reinterpret_cast<float2*>(plane)[it.pair(m)] = p[i][m];
+      }
     }
   }
-  __syncthreads();
-  slab_r2c(L, tid);
-  store_spec<NX, NY, NZ>(L.S, Pout + cz, tid);
+  x_forward_from_regs(L, p, tid);
+  y_forward_to_global(L, Pout + cz, tid);
 }
 
 // ---- adjoint kernels ---------------------------------------------------------
 
 // rho^_xi = c0^2 S^T y^{nt-1}, u^_xi = 0, W_xi = R2C(b_xi rho^_xi).
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_init(const float* __restrict__ ylast, WaveBuffers B,
-                                                                    WaveTables t, WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_adj_init(const float* __restrict__ ylast, WaveBuffers B,
+                                                           WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
+  constexpr int NT = kThreadsSlab;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int tid = threadIdx.x;
   int z, xi;
@@ -609,75 +890,71 @@ __global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_init(const float*
     for (int e = tid; e < D::SLAB_C; e += NT) B.spec[xi][cz + e] = zero;
     return;
   }
-  load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, tid);
+  load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[0];
-  const float2* y = reinterpret_cast<const float2*>(ylast);
-  float2 v[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i)
-    if (tid + i * NT < D::SLAB_P) v[i] = y[tid + i * NT];
+  float2 v[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(v, reinterpret_cast<const float2*>(ylast), tid);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const int yy = e / D::MX, n = e % D::MX;
-      const float2 r = make_float2(v[i].x * sc.c2, v[i].y * sc.c2);
-      rb[e] = r;
-      ub[e] = zero;
-      float b0, b1;
-      if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
-      else if (xi == 1) { b0 = b1 = L.py[yy]; }
-      else { b0 = b1 = bzz; }
-      L.S[yy * D::PITCH + n] = widen<V>(make_float2(b0 * r.x, b1 * r.y));
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        const int n = it.n(m);
+        const float2 r = make_float2(v[i][m].x * sc.c2, v[i][m].y * sc.c2);
+        rb[it.pair(m)] = r;
+        ub[it.pair(m)] = zero;
+        float b0, b1;
+        if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
+        else if (xi == 1) { b0 = b1 = L.py[it.y]; }
+        else { b0 = b1 = bzz; }
+        v[i][m] = make_float2(b0 * r.x, b1 * r.y);
+      }
     }
   }
-  __syncthreads();
-  slab_r2c(L, tid);
-  store_spec<NX, NY, NZ>(L.S, B.spec[xi] + cz, tid);
+  x_forward_from_regs(L, v, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, tid);
 }
 
 // u^_xi: uh = u^ + dt rho0 Dplus_xi(b rho^) (the pencil pass already applied the
 // multiplier), u^ <- a^2 uh, W_xi = R2C(a uh) in place.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int tid = threadIdx.x;
   int z, xi;
   slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
-  load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, tid);
-  load_spec<NX, NY, NZ>(L.S, B.spec[xi] + cz, 0, (const V*)nullptr, tid);
   float2* ub = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
-  float2 uold[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i)
-    if (tid + i * NT < D::SLAB_P) uold[i] = ub[tid + i * NT];
+  float2 uo[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(uo, ub, tid);
+  load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, (const V*)nullptr, 0, tid);
   const float azz = t.az[z];
   __syncthreads();
-  slab_c2r(L, tid);
+  y_inverse_from_global(L, B.spec[xi] + cz, 0, tid);
+  float2 g[D::IX0][D::RX0];
+  x_inverse_to_regs(L, g, tid);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const int y = e / D::MX, n = e % D::MX;
-      const float2 g = narrow(L.S[y * D::PITCH + n]);
-      float a0, a1;
-      if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
-      else if (xi == 1) { a0 = a1 = L.py[y]; }
-      else { a0 = a1 = azz; }
-      const float2 uo = uold[i];
-      const float2 uh = make_float2(uo.x + sc.dt_rho0 * g.x, uo.y + sc.dt_rho0 * g.y);
-      ub[e] = make_float2(a0 * a0 * uh.x, a1 * a1 * uh.y);
-      L.S[y * D::PITCH + n] = widen<V>(make_float2(a0 * uh.x, a1 * uh.y));
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        const int n = it.n(m);
+        float a0, a1;
+        if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
+        else if (xi == 1) { a0 = a1 = L.py[it.y]; }
+        else { a0 = a1 = azz; }
+        const float2 uh = make_float2(uo[i][m].x + sc.dt_rho0 * g[i][m].x, uo[i][m].y + sc.dt_rho0 * g[i][m].y);
+        ub[it.pair(m)] = make_float2(a0 * a0 * uh.x, a1 * a1 * uh.y);
+        g[i][m] = make_float2(a0 * uh.x, a1 * uh.y);
+      }
     }
   }
-  __syncthreads();
-  slab_r2c(L, tid);
-  store_spec<NX, NY, NZ>(L.S, B.spec[xi] + cz, tid);
+  x_forward_from_regs(L, g, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, tid);
 }
 
 // Pencil pass of the summed divergence: out = IFFT_z[ sum_xi kappa/N i k_xi
@@ -690,143 +967,151 @@ __global__ __launch_bounds__(kThreadsZ) void k_zdiv_sum(const float2* __restrict
                                                         float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
-  constexpr int TY = D::TY, W = 2 * TY;
-  __shared__ PencilLds<NX, NY, NZ, V, W> L;
+  __shared__ PencilLds<NX, NY, NZ, V, 1> L;
+  __shared__ V fy[3][D::TY];   // per component: the x or y factor by column (else 1)
+  __shared__ V fz[3][NZ];      // per component: the z factor by kz position (else 1)
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
-  const int kx = blockIdx.x / (NY / TY), p0 = (blockIdx.x % (NY / TY)) * TY;
-  load_pencil_tables(L, t, p0, tab.mmz, tab.mmy, tid);
+  const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
+  float2 r[D::IZ0][D::RZ0];
+  z_load<NX, NY, NZ>(r, W0, kx, p0, tid);
+  const V one = mkc<V>((Sc)1, (Sc)0);
+  load_pencil_tables(L, t, p0, one, (const V*)nullptr, (const V*)nullptr, tid);
+  for (int i = tid; i < NZ; i += kThreadsZ) {
+    fz[0][i] = one;
+    fz[1][i] = one;
+    fz[2][i] = tab.mmz[i];
+  }
+  if (tid < D::TY) {
+    fy[0][tid] = tab.mmx[kx];
+    fy[1][tid] = tab.mmy[p0 + tid];
+    fy[2][tid] = one;
+  }
   const Sc hx = tab.hx[kx];
-  const V mxk = tab.mmx[kx];
-  Sc kap[D::ZIT];
+  __syncthreads();
+  // kappa is common to the three terms: sum m_xi FFT_z(W_xi) first, scale once
+  V acc[D::IZ1][D::MZB];
+#pragma unroll
+  for (int i = 0; i < D::IZ1; ++i)
+#pragma unroll
+    for (int k1 = 0; k1 < D::MZB; ++k1) acc[i][k1] = mkc<V>((Sc)0, (Sc)0);
 #pragma unroll 1
   for (int xi = 0; xi < 3; ++xi) {
-    const float2* H = xi == 0 ? W0 : (xi == 1 ? W1 : W2);
-    load_tile<NX, NY, NZ>(L.T, W, 0, H, kx, p0, tid);
+    int tl = tid;   // opaque copy: addresses are recomputed per component, not kept live
+    asm volatile("" : "+v"(tl));
+    z_fwd0<NX, NY, NZ>(L.T[0], r, L.twz, tl);
+    if (xi < 2) z_load<NX, NY, NZ>(r, xi == 0 ? W1 : W2, kx, p0, tl);   // next component in flight
     __syncthreads();
-    if (xi == 0) {
+    V v[D::IZ1][D::MZB];
+    z_fwd1<NX, NY, NZ>(L.T[0], v, tl);
 #pragma unroll
-      for (int i = 0; i < D::ZIT; ++i) {
-        const int e = tid + i * kThreadsZ;
-        const int q = (e / TY) % NZ, j = e % TY;
-        kap[i] = sinc_of_sq(hx * hx + L.hy[j] * L.hy[j] + L.hz[q] * L.hz[q]) * (Sc)inv_ntot;
-      }
-    }
-    fft_forward<NZ, true, TY, 1, W, kThreadsZ>(L.T, L.twz, tid);
+    for (int i = 0; i < D::IZ1; ++i) {
+      const int b = tl + i * kThreadsZ;
+      const int col = b % D::TY, mb = (b / D::TY) % D::RZ0;
 #pragma unroll
-    for (int i = 0; i < D::ZIT; ++i) {
-      const int e = tid + i * kThreadsZ;
-      if (e < NZ * TY) {
-        const int q = e / TY, j = e % TY;
-        const V m = xi == 0 ? mxk : (xi == 1 ? L.my[j] : L.mz[q]);
-        const V v = cmul(cscale(L.T[q * W + j], kap[i]), m);
-        L.T[q * W + TY + j] = xi == 0 ? v : cadd(L.T[q * W + TY + j], v);
-      }
+      for (int k1 = 0; k1 < D::MZB; ++k1)
+        acc[i][k1] = cadd(acc[i][k1], cmul(v[i][k1], cmul(fy[xi][col], fz[xi][D::MZB * mb + k1])));
     }
     __syncthreads();
   }
-  fft_inverse<NZ, true, TY, 1, W, kThreadsZ>(L.T + TY, L.twz, tid);
-  store_tile<NX, NY, NZ>(L.T, W, TY, out, kx, p0, tid);
+#pragma unroll
+  for (int i = 0; i < D::IZ1; ++i) {
+    const int b = tid + i * kThreadsZ;
+    const int col = b % D::TY, mb = (b / D::TY) % D::RZ0;
+#pragma unroll
+    for (int k1 = 0; k1 < D::MZB; ++k1)
+      acc[i][k1] = cscale(acc[i][k1], kappa_n(hx, L.hy[col], L.hz[D::MZB * mb + k1], inv_ntot));
+  }
+  z_inv1<NX, NY, NZ>(L.T[0], acc, tid);
+  __syncthreads();
+  z_inv0_store<NX, NY, NZ>(L.T[0], out, kx, p0, L.twz, tid);
 }
 
 // rho^_xi <- b^2 rho^_xi + c0^2 dt/rho0 q + c0^2 S^T y^n; then W_xi = R2C(b rho^_xi),
 // or on the last (final != 0) step W_xi = R2C(u^_xi) for the initial-condition transpose.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_rho(const float2* __restrict__ Qs, WaveBuffers B,
-                                                                   const float* __restrict__ yplane, WaveTables t,
-                                                                   WaveScalars sc, int final_step) {
+__global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restrict__ Qs, WaveBuffers B,
+                                                          const float* __restrict__ yplane, WaveTables t,
+                                                          WaveScalars sc, int final_step) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int tid = threadIdx.x;
   int z, xi;
   slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, tid);
-  load_spec<NX, NY, NZ>(L.S, Qs + cz, 0, (const V*)nullptr, tid);
   float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
   const float2* ub = reinterpret_cast<const float2*>(B.u[xi]) + rz;
-  const float2* y = reinterpret_cast<const float2*>(yplane);
-  float2 rold[EPT], src[EPT], uf[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      rold[i] = rb[e];
-      src[i] = z == 0 ? y[e] : make_float2(0.f, 0.f);
-      uf[i] = final_step ? ub[e] : make_float2(0.f, 0.f);
-    }
-  }
+  float2 ro[D::IX0][D::RX0], src[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(ro, rb, tid);
+  if (z == 0) load_real<NX, NY, NZ>(src, reinterpret_cast<const float2*>(yplane), tid);   // data source
+  load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
   __syncthreads();
-  slab_c2r(L, tid);
+  y_inverse_from_global(L, Qs + cz, 0, tid);
+  float2 q[D::IX0][D::RX0];
+  x_inverse_to_regs(L, q, tid);
   const float qs = sc.c2 * sc.dt_over_rho0;
+  const float ss = z == 0 ? sc.c2 : 0.f;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const int yy = e / D::MX, n = e % D::MX;
-      const float2 q = narrow(L.S[yy * D::PITCH + n]);
-      float b0, b1;
-      if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
-      else if (xi == 1) { b0 = b1 = L.py[yy]; }
-      else { b0 = b1 = bzz; }
-      const float2 ro = rold[i];
-      const float2 rn = make_float2(b0 * b0 * ro.x + qs * q.x + sc.c2 * src[i].x,
-                                    b1 * b1 * ro.y + qs * q.y + sc.c2 * src[i].y);
-      rb[e] = rn;
-      L.S[yy * D::PITCH + n] = widen<V>(final_step ? uf[i] : make_float2(b0 * rn.x, b1 * rn.y));
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        const int n = it.n(m);
+        float b0, b1;
+        if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
+        else if (xi == 1) { b0 = b1 = L.py[it.y]; }
+        else { b0 = b1 = bzz; }
+        const float2 sv = z == 0 ? src[i][m] : make_float2(0.f, 0.f);
+        const float2 rn = make_float2(b0 * b0 * ro[i][m].x + qs * q[i][m].x + ss * sv.x,
+                                      b1 * b1 * ro[i][m].y + qs * q[i][m].y + ss * sv.y);
+        rb[it.pair(m)] = rn;
+        q[i][m] = make_float2(b0 * rn.x, b1 * rn.y);
+      }
     }
   }
-  __syncthreads();
-  slab_r2c(L, tid);
-  store_spec<NX, NY, NZ>(L.S, B.spec[xi] + cz, tid);
+  // last step: the initial-condition transpose needs R2C(u^) instead (read once per adjoint)
+  if (final_step) load_real<NX, NY, NZ>(q, ub, tid);
+  x_forward_from_regs(L, q, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, tid);
 }
 
 // p = (rho^_x + rho^_y + rho^_z)/(3 c0^2) - dt/(2 rho0) sum_xi Dminus_xi u^_xi.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(SlabThreads<V>::value) void k_adj_final(const float2* __restrict__ Qs, WaveBuffers B,
-                                                                     float* __restrict__ pout, WaveTables t,
-                                                                     WaveScalars sc, int with_velocity) {
+__global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __restrict__ Qs, WaveBuffers B,
+                                                            float* __restrict__ pout, WaveTables t,
+                                                            WaveScalars sc, int with_velocity) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
-  constexpr int EPT = (D::SLAB_P + NT - 1) / NT;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int z = blockIdx.x, tid = threadIdx.x;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  const float2* r0 = reinterpret_cast<const float2*>(B.rho[0]) + rz;
-  const float2* r1 = reinterpret_cast<const float2*>(B.rho[1]) + rz;
-  const float2* r2 = reinterpret_cast<const float2*>(B.rho[2]) + rz;
-  float2 rs[EPT];
+  float2 g[D::IX0][D::RX0];
   if (with_velocity) {
-    load_slab_tables(L, t, nullptr, nullptr, tid);
-    load_spec<NX, NY, NZ>(L.S, Qs + cz, 0, (const V*)nullptr, tid);
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      const float2 a = r0[e], b = r1[e], c = r2[e];
-      rs[i] = make_float2((a.x + b.x + c.x) * sc.inv_3c2, (a.y + b.y + c.y) * sc.inv_3c2);
-    }
-  }
-  if (with_velocity) {
+    load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
     __syncthreads();
-    slab_c2r(L, tid);
+    y_inverse_from_global(L, Qs + cz, 0, tid);
+    x_inverse_to_regs(L, g, tid);
   }
+  float2 r0[D::IX0][D::RX0], r1[D::IX0][D::RX0], r2[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(r0, reinterpret_cast<const float2*>(B.rho[0]) + rz, tid);
+  load_real<NX, NY, NZ>(r1, reinterpret_cast<const float2*>(B.rho[1]) + rz, tid);
+  load_real<NX, NY, NZ>(r2, reinterpret_cast<const float2*>(B.rho[2]) + rz, tid);
   float2* p = reinterpret_cast<float2*>(pout) + rz;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (e < D::SLAB_P) {
-      float2 v = rs[i];
-      if (with_velocity) {
-        const float2 g = narrow(L.S[(e / D::MX) * D::PITCH + e % D::MX]);
-        v.x -= sc.half_dt_over_rho0 * g.x;
-        v.y -= sc.half_dt_over_rho0 * g.y;
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) {
+        float2 v = make_float2((r0[i][m].x + r1[i][m].x + r2[i][m].x) * sc.inv_3c2,
+                               (r0[i][m].y + r1[i][m].y + r2[i][m].y) * sc.inv_3c2);
+        if (with_velocity) {
+          v.x -= sc.half_dt_over_rho0 * g[i][m].x;
+          v.y -= sc.half_dt_over_rho0 * g[i][m].y;
+        }
+        p[it.pair(m)] = v;
       }
-      p[e] = v;
     }
   }
 }
@@ -849,7 +1134,7 @@ template <int NX, int NY, int NZ, typename V>
 hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
                         const float* p0, float* planes, int nt, hipStream_t st, KernelTimer* kt) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
+  constexpr int NT = kThreadsSlab;
   const size_t npix = (size_t)NX * NY;
   k_fwd_init<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(p0, B, planes, t, sc);
   for (int n = 0; n < nt - 1; ++n) {
@@ -876,7 +1161,7 @@ template <int NX, int NY, int NZ, typename V>
 hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
                         const float* planes, float* p, int nt, hipStream_t st, KernelTimer* kt) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = SlabThreads<V>::value;
+  constexpr int NT = kThreadsSlab;
   const size_t npix = (size_t)NX * NY;
   k_adj_init<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(planes + (size_t)(nt - 1) * npix, B, t, sc);
   if (nt == 1) {

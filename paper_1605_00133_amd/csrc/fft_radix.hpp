@@ -24,7 +24,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
 
 namespace pat {
 
@@ -173,25 +172,35 @@ __device__ __forceinline__ void dft_r(V* a) {
   else if constexpr (R == 16) dft16<INV>(a);
 }
 
-// Stage-0 twiddles of butterfly n1: a[k] *= w^k (forward) or conj(w)^k (inverse)
-// for k = 1..R-1, w = w_L^n1 = tw[n1] from the L-point table exp(-2 pi i j / L).
-// In FP64 the powers are built by repeated multiplication (a relative error of
-// a few 1e-16, far below the FP32 storage rounding) so one table read serves
-// the whole butterfly; in FP32 every power is read from the table.
-template <int R, bool INV, typename V>
-__device__ __forceinline__ void stage_twiddle(V* a, const V* tw, int n1) {
-  if constexpr (std::is_same<V, double2>::value) {
-    const V w = tw[n1];
-    V wk = w;
+// Stage-0 twiddles of butterfly n1 (< M): a[k] *= w^k (forward) or conj(w)^k
+// (inverse) for k = 1..R-1, w = exp(-2 pi i n1 / L), read from the transposed
+// table twT[k M + n1] = exp(-2 pi i n1 k / L) (L = R M entries). Threads with
+// consecutive n1 read consecutive slots, threads with equal n1 the same slot.
+template <int R, int M, bool INV, typename V>
+__device__ __forceinline__ void stage_twiddle(V* a, const V* twT, int n1) {
 #pragma unroll
-    for (int k = 1; k < R; ++k) {
-      a[k] = INV ? cmulconj(a[k], wk) : cmul(a[k], wk);
-      if (k + 1 < R) wk = cmul(wk, w);
-    }
-  } else {
+  for (int k = 1; k < R; ++k) a[k] = INV ? cmulconj(a[k], twT[k * M + n1]) : cmul(a[k], twT[k * M + n1]);
+}
+
+// As stage_twiddle, with the powers of w = twT[M + n1] built by repeated
+// multiplication in registers (one table read; a relative error of a few
+// 1e-16 in FP64): for FP64 butterflies whose table reads would otherwise all
+// be held in registers at once.
+template <int R, int M, bool INV, typename V>
+__device__ __forceinline__ void stage_twiddle_pow(V* a, const V* twT, int n1) {
+  const V w = twT[M + n1];
+  V wk = w;
 #pragma unroll
-    for (int k = 1; k < R; ++k) a[k] = INV ? cmulconj(a[k], tw[n1 * k]) : cmul(a[k], tw[n1 * k]);
+  for (int k = 1; k < R; ++k) {
+    a[k] = INV ? cmulconj(a[k], wk) : cmul(a[k], wk);
+    if (k + 1 < R) wk = cmul(wk, w);
   }
+}
+
+// Fill twT[k M + n1] = tw[n1 k] from the natural L-point table tw (k < R, n1 < M).
+template <int R, int M, typename V, int NT>
+__device__ __forceinline__ void fill_stage_table(V* twT, const V* tw, int tid) {
+  for (int i = tid; i < R * M; i += NT) twT[i] = tw[(i % M) * (i / M)];
 }
 
 }  // namespace pat

@@ -36,34 +36,44 @@
 // -> pencil(sum of the three divergences: 3 in, 1 out) -> slab(rho^ + source).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_radix.hpp"
 #include "wave_common.hpp"
 
 namespace pat {
 
-constexpr int kThreadsZ = 128;
+constexpr int kThreadsZ = 256;
 constexpr int kThreadsSlab = 512;
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Slot of row index idx in an LDS slab row: an XOR of its low three bits with
+// the next three. Every exchange below then touches 8 distinct 16-byte slots
+// per 8 lanes (together with a row pitch = 4 mod 8), whether lanes run along
+// a row, down a column or over the butterflies of neighbouring rows.
+__host__ __device__ constexpr int slot_of(int idx) { return idx ^ ((idx >> 3) & 7); }
+__host__ __device__ constexpr int slab_pitch(int mx) {   // smallest pitch > slot_of(mx), = 4 mod 8
+  return slot_of(mx) + 1 + ((4 - (slot_of(mx) + 1) % 8) + 8) % 8;
+}
 
 template <int NX, int NY, int NZ>
 struct Dims {
   static constexpr int MX = NX / 2;          // complex length of a packed real row
   static constexpr int NKX = MX + 1;         // half-spectrum length
-  static constexpr int PITCH = NKX;          // LDS row pitch (complex), odd
+  static constexpr int PITCH = slab_pitch(MX);   // LDS row pitch (complex), = 4 mod 8
   static constexpr int SLAB_C = NKX * NY;    // complex values per slab spectrum
   static constexpr int SLAB_P = NY * MX;     // float2 pairs per real slab
   // two-stage splits L = R0 * M of the x (packed), y and z transforms
   static constexpr int RX0 = fft_radix(MX, 0), MXB = MX / RX0;
   static constexpr int RY0 = fft_radix(NY, 0), MYB = NY / RY0;
   static constexpr int RZ0 = fft_radix(NZ, 0), MZB = NZ / RZ0;
-  // slab work items per phase and their loop counts over kThreadsSlab threads
-  static constexpr int NY1 = NKX * RY0;      // y stage-1 butterflies (M-point)
-  static constexpr int NY0 = NKX * MYB;      // y stage-0 butterflies (R0-point)
-  static constexpr int NXP = NY * (RX0 / 2); // x stage-1 pairs of butterflies (+ real-FFT split)
-  static constexpr int NX0 = NY * MXB;       // x stage-0 butterflies
-  static constexpr int IY1 = cdiv(NY1, kThreadsSlab), IY0 = cdiv(NY0, kThreadsSlab);
-  static constexpr int IXP = cdiv(NXP, kThreadsSlab), IX0 = cdiv(NX0, kThreadsSlab);
+  // x phases: every wave owns RPW whole rows, so exchanges inside a row never
+  // leave the wave; per lane IX0 stage-0 butterflies and IXP pair items
+  static constexpr int NWAVES = kThreadsSlab / 64;
+  static constexpr int PPR = RX0 / 2;        // pair items (real-FFT split) per row
+  static constexpr int RPW = NY / NWAVES > 0 ? NY / NWAVES : 1;
+  static constexpr int IX0 = cdiv(RPW * MXB, 64), IXP = cdiv(RPW * PPR, 64);
   // pencil tiles
   static constexpr int TY = NY >= 16 ? 16 : NY;
   static constexpr int NTILE = NKX * (NY / TY);
@@ -71,6 +81,8 @@ struct Dims {
   static constexpr int NZ1 = TY * RZ0;       // z stage-1 butterflies per tile
   static constexpr int IZ0 = cdiv(NZ0, kThreadsZ), IZ1 = cdiv(NZ1, kThreadsZ);
   static_assert(RX0 >= 4 && RX0 % 2 == 0, "x split needs an even first radix");
+  static_assert(NY % NWAVES == 0 || NY < NWAVES, "rows must split evenly over the waves");
+  static_assert(PITCH >= slot_of(MX) + 1 && PITCH % 8 == 4, "slab pitch");
 };
 
 // Register arrays of the real-space layout (per slot i, value m) and of a pencil tile.
@@ -116,16 +128,16 @@ __device__ __forceinline__ double sinc_of_sq(double s) {
 }
 
 // ---- LDS workspace of a slab workgroup ---------------------------------------
-// S holds the slab as rows y (0..NY-1) of PITCH complex slots; column kx of the
-// spectrum is S[.][kx]. The same rows hold the packed real row (index n, the
-// pair x = 2n, 2n+1) and the intermediate stage of the x transform.
+// S holds the slab as rows y (0..NY-1) of PITCH complex slots; index idx of a
+// row (column kx of the spectrum, or an intermediate index of the x
+// transform) lives in slot slot_of(idx), see sidx().
 template <int NX, int NY, int NZ, typename V>
 struct SlabLds {
   using D = Dims<NX, NY, NZ>;
   V S[NY * D::PITCH];
-  V twx[D::MX];                        // exp(-2 pi i j / MX)
+  V twx[D::MX];                        // x stage-0 twiddles, transposed table (MX points)
   V twn[D::NKX];                       // exp(-2 pi i k / NX), k <= MX (real-FFT split)
-  V twy[NY];                           // exp(-2 pi i j / NY)
+  V twy[NY];                           // y stage-0 twiddles, transposed table (NY points)
   V mul[NY > D::NKX ? NY : D::NKX];    // optional derivative factor by kx or by ky_pos
   float px[NX];                        // PML profile along x of the component handled
   float py[NY];                        // PML profile along y
@@ -140,9 +152,9 @@ __device__ __forceinline__ void load_slab_tables(SlabLds<NX, NY, NZ, V>& L, cons
   using D = Dims<NX, NY, NZ>;
   constexpr int NT = kThreadsSlab;
   const auto& T = TabSel<V>::get(t);
-  for (int i = tid; i < D::MX; i += NT) L.twx[i] = T.tw_mx[i];
+  fill_stage_table<D::RX0, D::MXB, V, NT>(L.twx, T.tw_mx, tid);
   for (int i = tid; i < D::NKX; i += NT) L.twn[i] = T.tw_nx[i];
-  for (int i = tid; i < NY; i += NT) L.twy[i] = T.tw_y[i];
+  fill_stage_table<D::RY0, D::MYB, V, NT>(L.twy, T.tw_y, tid);
   if (mult_mode == 1)
     for (int i = tid; i < D::NKX; i += NT) L.mul[i] = mult[i];
   else if (mult_mode == 2)
@@ -153,21 +165,31 @@ __device__ __forceinline__ void load_slab_tables(SlabLds<NX, NY, NZ, V>& L, cons
     for (int i = tid; i < NY; i += NT) L.py[i] = pml_y[i];
 }
 
-// Real-space register layout shared by every slab kernel: loop slot i of a
-// thread is item b = tid + i * kThreadsSlab (valid while b < NX0), the row
-// y = b / MXB and offset n1 = b % MXB; value m (< RX0) is the packed pair
-// n = n1 + MXB m of row y, i.e. x = 2n, 2n + 1, at float2 index y * MX + n of
-// the slab.
+__device__ __forceinline__ int sidx(int row, int idx, int pitch) { return row * pitch + slot_of(idx); }
+
+// Orders LDS traffic between the lanes of one wave (an exchange inside rows the
+// wave owns needs no workgroup barrier: LDS runs a wave's operations in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Real-space register layout shared by every slab kernel: wave w owns rows
+// [w RPW, (w+1) RPW); slot i of lane l is item e = l + 64 i of the wave (valid
+// while e < RPW MXB), offset n1 = e % MXB, row y = w RPW + e / MXB; value m
+// (< RX0) is the packed pair n = n1 + MXB m of row y, i.e. x = 2n, 2n + 1, at
+// float2 index y * MX + n of the slab.
 template <int NX, int NY, int NZ>
 struct RowItem {
   using D = Dims<NX, NY, NZ>;
   int y, n1;
   bool ok;
   __device__ __forceinline__ RowItem(int tid, int i) {
-    const int b = tid + i * kThreadsSlab;
-    ok = b < D::NX0;
-    y = b / D::MXB;
-    n1 = b % D::MXB;
+    const int e = (tid & 63) + 64 * i;
+    ok = e < D::RPW * D::MXB && (tid >> 6) * D::RPW < NY;
+    y = (tid >> 6) * D::RPW + e / D::MXB;
+    n1 = e % D::MXB;
   }
   __device__ __forceinline__ int pair(int m) const { return y * D::MX + n1 + D::MXB * m; }
   __device__ __forceinline__ int n(int m) const { return n1 + D::MXB * m; }
@@ -175,8 +197,7 @@ struct RowItem {
 
 // Load one real slab (float2 pairs) in the register layout.
 template <int NX, int NY, int NZ>
-__device__ __forceinline__ void load_real(RealRegs<NX, NY, NZ>& r,
-                                          const float2* __restrict__ src, int tid) {
+__device__ __forceinline__ void load_real(RealRegs<NX, NY, NZ>& r, const float2* __restrict__ src, int tid) {
   using D = Dims<NX, NY, NZ>;
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
@@ -190,30 +211,91 @@ __device__ __forceinline__ void load_real(RealRegs<NX, NY, NZ>& r,
 
 // ---- slab transforms -------------------------------------------------------
 
+// Work items of the y stages. Columns kx < MX are the main items, laid out so
+// that a wave of 64 lanes holds 64 consecutive columns of one butterfly (for
+// MX a multiple of 64 the butterfly index, and hence its twiddles, is
+// wave-uniform); the Nyquist column kx = MX is an extra item for the first threads.
+//   stage 1 (M-point blocks mb < R0): main item b -> kx = b % MX, mb = b / MX
+//   stage 0 (R0-point butterflies n1 < M): main item b -> kx = b % MX, n1 = b / MX
+template <int NX, int NY, int NZ>
+struct YItems {
+  using D = Dims<NX, NY, NZ>;
+  static constexpr int N1 = D::MX * D::RY0, I1 = cdiv(N1, kThreadsSlab);   // stage 1 main
+  static constexpr int N0 = D::MX * D::MYB, I0 = cdiv(N0, kThreadsSlab);   // stage 0 main
+  static constexpr bool UNIFORM = D::MX % 64 == 0;
+  static __device__ __forceinline__ bool s1(int tid, int i, int& kx, int& mb) {
+    if (i < I1) {
+      const int b = tid + i * kThreadsSlab;
+      kx = b % D::MX;
+      mb = b / D::MX;
+      return b < N1;
+    }
+    kx = D::MX;
+    mb = tid;
+    return tid < D::RY0;
+  }
+  static __device__ __forceinline__ bool s0(int tid, int i, int& kx, int& n1) {
+    if (i < I0) {
+      const int b = tid + i * kThreadsSlab;
+      kx = b % D::MX;
+      n1 = b / D::MX;
+      return b < N0;
+    }
+    kx = D::MX;
+    n1 = tid;
+    return tid < D::MYB;
+  }
+};
+
+template <typename V> using ConstTab = __attribute__((address_space(4))) const V;
+
+// y stage-0 twiddles of butterfly n1: for main items with a wave-uniform n1 they
+// come through the scalar cache from the natural table tw_y (global, read-only);
+// otherwise from the transposed LDS table.
+template <int NX, int NY, int NZ, bool INV, typename V>
+__device__ __forceinline__ void y_twiddle(V* a, const SlabLds<NX, NY, NZ, V>& L, const V* __restrict__ twg,
+                                          int n1, bool main_item) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int M = D::MYB, R0 = D::RY0;
+  if constexpr (M > 1) {
+    if (YItems<NX, NY, NZ>::UNIFORM && main_item) {
+      using Sc = typename ScalarOf<V>::T;
+      const int n1u = __builtin_amdgcn_readfirstlane(n1);
+      ConstTab<Sc>* t = (ConstTab<Sc>*)twg;   // (re, im) pairs
+#pragma unroll
+      for (int k = 1; k < R0; ++k) {
+        const V w = mkc<V>(t[2 * n1u * k], t[2 * n1u * k + 1]);
+        a[k] = INV ? cmulconj(a[k], w) : cmul(a[k], w);
+      }
+    } else {
+      stage_twiddle<R0, M, INV>(a, L.twy, n1);
+    }
+  }
+}
+
 // y inverse transform of the slab spectrum g[kx][ky_pos] (times an optional
 // derivative factor L.mul by kx (mode 1) or ky_pos (mode 2)), read straight
-// from HBM into the stage-1 butterflies; leaves S[y][kx] in natural y order.
-// Caller syncs before (tables); ends synced.
+// from HBM into the stage-1 butterflies; leaves the rows in natural y order
+// (index kx). Caller syncs before (tables); ends synced.
 template <int NX, int NY, int NZ, typename V>
 __device__ __forceinline__ void y_inverse_from_global(SlabLds<NX, NY, NZ, V>& L, const float2* __restrict__ g,
-                                                      int mode, int tid) {
+                                                      int mode, const V* __restrict__ twg, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = kThreadsSlab, M = D::MYB, R0 = D::RY0;
-  float2 r[D::IY1][M];
+  using Y = YItems<NX, NY, NZ>;
+  constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
+  float2 r[Y::I1 + 1][M];
 #pragma unroll
-  for (int i = 0; i < D::IY1; ++i) {   // every global load in flight before any arithmetic
-    const int b = tid + i * NT;
-    if (b < D::NY1) {
-      const int kx = b % D::NKX, mb = b / D::NKX;
+  for (int i = 0; i <= Y::I1; ++i) {   // every global load in flight before any arithmetic
+    int kx, mb;
+    if (Y::s1(tid, i, kx, mb)) {
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) r[i][k1] = g[kx * NY + M * mb + k1];
     }
   }
 #pragma unroll
-  for (int i = 0; i < D::IY1; ++i) {
-    const int b = tid + i * NT;
-    if (b < D::NY1) {
-      const int kx = b % D::NKX, mb = b / D::NKX;
+  for (int i = 0; i <= Y::I1; ++i) {
+    int kx, mb;
+    if (Y::s1(tid, i, kx, mb)) {
       V a[M];
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
@@ -223,56 +305,56 @@ __device__ __forceinline__ void y_inverse_from_global(SlabLds<NX, NY, NZ, V>& L,
       }
       dft_r<M, true>(a);
 #pragma unroll
-      for (int n1 = 0; n1 < M; ++n1) L.S[(M * mb + n1) * D::PITCH + kx] = a[n1];
+      for (int n1 = 0; n1 < M; ++n1) L.S[sidx(M * mb + n1, kx, P)] = a[n1];
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < D::IY0; ++i) {
-    const int b = tid + i * NT;
-    if (b < D::NY0) {
-      const int kx = b % D::NKX, n1 = b / D::NKX;
+  for (int i = 0; i <= Y::I0; ++i) {
+    int kx, n1;
+    if (Y::s0(tid, i, kx, n1)) {
       V a[R0];
 #pragma unroll
-      for (int m = 0; m < R0; ++m) a[m] = L.S[(n1 + M * m) * D::PITCH + kx];
-      if constexpr (M > 1) stage_twiddle<R0, true>(a, L.twy, n1);
+      for (int m = 0; m < R0; ++m) a[m] = L.S[sidx(n1 + M * m, kx, P)];
+      y_twiddle<NX, NY, NZ, true>(a, L, twg, n1, i < Y::I0);
       dft_r<R0, true>(a);
 #pragma unroll
-      for (int m = 0; m < R0; ++m) L.S[(n1 + M * m) * D::PITCH + kx] = a[m];
+      for (int m = 0; m < R0; ++m) L.S[sidx(n1 + M * m, kx, P)] = a[m];
     }
   }
   __syncthreads();
 }
 
-// y forward transform of S[y][kx] (natural y) into the slab spectrum g[kx][ky_pos]:
-// stage 0 in LDS, stage 1 straight from registers to HBM. Caller syncs before.
+// y forward transform of the rows (natural y, index kx) into the slab spectrum
+// g[kx][ky_pos]: stage 0 in LDS, stage 1 straight from registers to HBM.
+// Caller syncs before.
 template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void y_forward_to_global(SlabLds<NX, NY, NZ, V>& L, float2* __restrict__ g, int tid) {
+__device__ __forceinline__ void y_forward_to_global(SlabLds<NX, NY, NZ, V>& L, float2* __restrict__ g,
+                                                    const V* __restrict__ twg, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int NT = kThreadsSlab, M = D::MYB, R0 = D::RY0;
+  using Y = YItems<NX, NY, NZ>;
+  constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
 #pragma unroll
-  for (int i = 0; i < D::IY0; ++i) {
-    const int b = tid + i * NT;
-    if (b < D::NY0) {
-      const int kx = b % D::NKX, n1 = b / D::NKX;
+  for (int i = 0; i <= Y::I0; ++i) {
+    int kx, n1;
+    if (Y::s0(tid, i, kx, n1)) {
       V a[R0];
 #pragma unroll
-      for (int m = 0; m < R0; ++m) a[m] = L.S[(n1 + M * m) * D::PITCH + kx];
+      for (int m = 0; m < R0; ++m) a[m] = L.S[sidx(n1 + M * m, kx, P)];
       dft_r<R0, false>(a);
-      if constexpr (M > 1) stage_twiddle<R0, false>(a, L.twy, n1);
+      y_twiddle<NX, NY, NZ, false>(a, L, twg, n1, i < Y::I0);
 #pragma unroll
-      for (int k = 0; k < R0; ++k) L.S[(n1 + M * k) * D::PITCH + kx] = a[k];
+      for (int k = 0; k < R0; ++k) L.S[sidx(n1 + M * k, kx, P)] = a[k];
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < D::IY1; ++i) {
-    const int b = tid + i * NT;
-    if (b < D::NY1) {
-      const int kx = b % D::NKX, mb = b / D::NKX;
+  for (int i = 0; i <= Y::I1; ++i) {
+    int kx, mb;
+    if (Y::s1(tid, i, kx, mb)) {
       V a[M];
 #pragma unroll
-      for (int k1 = 0; k1 < M; ++k1) a[k1] = L.S[(M * mb + k1) * D::PITCH + kx];
+      for (int k1 = 0; k1 < M; ++k1) a[k1] = L.S[sidx(M * mb + k1, kx, P)];
       dft_r<M, false>(a);
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) g[kx * NY + M * mb + k1] = narrow(a[k1]);
@@ -303,108 +385,94 @@ __device__ __forceinline__ V split_inv(V xk, V xp, V w) {   // 2 Z[k] from X[k],
   return mkc<V>(s.x - wd.y, s.y + wd.x);
 }
 
-// Twiddles w^(b + R0 k1), k1 = 0, 1, ..., from the table exp(-2 pi i k / NX),
-// k <= MX: FP64 steps by w^R0 (one multiply per value), FP32 reads each.
-template <int R0, typename V>
-struct SplitTwiddle {
-  const V* twn;
-  int b;
-  V cur, step;
-  __device__ __forceinline__ SplitTwiddle(const V* t, int b_) : twn(t), b(b_) {
-    if constexpr (std::is_same<V, double2>::value) {
-      cur = twn[b];
-      step = twn[R0];
-    }
-  }
-  // value for k1; must be called with k1 = 0, 1, 2, ... in order
-  __device__ __forceinline__ V at(int k1) {
-    if constexpr (std::is_same<V, double2>::value) {
-      if (k1 > 0) cur = cmul(cur, step);
-      return cur;
-    } else {
-      return twn[b + R0 * k1];
-    }
-  }
-};
-
+// Pair item of the x phases: slot i of lane l is item e = l + 64 i of its wave
+// (valid while e < RPW PPR): g = e % PPR, row y = w RPW + e / PPR.
 template <int NX, int NY, int NZ>
 struct PairItem {
   using D = Dims<NX, NY, NZ>;
   int y, g, ma, mb;
   bool ok;
   __device__ __forceinline__ PairItem(int tid, int i) {
-    const int b = tid + i * kThreadsSlab;
-    ok = b < D::NXP;
-    y = b % NY;
-    g = b / NY;
+    const int e = (tid & 63) + 64 * i;
+    ok = e < D::RPW * D::PPR && (tid >> 6) * D::RPW < NY;
+    y = (tid >> 6) * D::RPW + e / D::PPR;
+    g = e % D::PPR;
     ma = g;
     mb = g == 0 ? D::RX0 / 2 : D::RX0 - g;
   }
 };
 
-// Rows S[y][kx] (natural kx, X[0..MX]) -> inverse x transform -> packed real
-// pairs in the register layout (unnormalised). Caller syncs before.
+// Rows (natural kx, X[0..MX]) -> inverse x transform -> packed real pairs in
+// the register layout (unnormalised). Caller syncs before. Every exchange
+// stays inside the rows of one wave.
 template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L,
-                                                  RealRegs<NX, NY, NZ>& out,
-                                                  int tid) {
+__device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, RealRegs<NX, NY, NZ>& out, int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX;
+  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX, P = D::PITCH;
   V za[D::IXP][M], zb[D::IXP][M];
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
     const PairItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      const V* row = L.S + it.y * D::PITCH;
       V xa[M], xb[M];
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
-        xa[k1] = row[it.ma + R0 * k1];
-        xb[k1] = row[it.mb + R0 * k1];
+        xa[k1] = L.S[sidx(it.y, it.ma + R0 * k1, P)];
+        xb[k1] = L.S[sidx(it.y, it.mb + R0 * k1, P)];
       }
-      const V xm = row[MX];
-      SplitTwiddle<R0, V> wa(L.twn, it.ma), wb(L.twn, it.mb);
-      // (branches rather than selects keep xa, xb in registers)
-      if (it.g != 0) {
+      const V xm = L.S[sidx(it.y, MX, P)];
+      const V* wa = L.twn + it.ma;   // w^k for k = ma + R0 k1 at wa[R0 k1]
+      const V* wb = L.twn + it.mb;
+      // Partners are taken two at a time so each input dies as its outputs are
+      // formed (branches rather than selects keep xa, xb in registers).
+      if (it.g != 0) {   // k = ma + R0 k1 pairs with mb + R0 (M-1-k1)
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) {
-          za[i][k1] = split_inv(xa[k1], xb[M - 1 - k1], wa.at(k1));
-          zb[i][k1] = split_inv(xb[k1], xa[M - 1 - k1], wb.at(k1));
+          const V a = xa[k1], b = xb[M - 1 - k1];
+          za[i][k1] = split_inv(a, b, wa[R0 * k1]);
+          zb[i][M - 1 - k1] = split_inv(b, a, wb[R0 * (M - 1 - k1)]);
         }
-      } else {
+      } else {           // block 0 pairs with itself (and X[MX]), block R0/2 with itself
 #pragma unroll
-        for (int k1 = 0; k1 < M; ++k1) {
-          za[i][k1] = split_inv(xa[k1], k1 == 0 ? xm : xa[(M - k1) % M], wa.at(k1));
-          zb[i][k1] = split_inv(xb[k1], xb[M - 1 - k1], wb.at(k1));
+        for (int k1 = 0; k1 <= M / 2; ++k1) {
+          const int k2 = (M - k1) % M;
+          const V a = xa[k1], b = k1 == 0 ? xm : xa[k2];
+          za[i][k1] = split_inv(a, b, wa[R0 * k1]);
+          if (k2 != k1) za[i][k2] = split_inv(b, a, wa[R0 * k2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < (M + 1) / 2; ++k1) {
+          const int k2 = M - 1 - k1;
+          const V a = xb[k1], b = xb[k2];
+          zb[i][k1] = split_inv(a, b, wb[R0 * k1]);
+          if (k2 != k1) zb[i][k2] = split_inv(b, a, wb[R0 * k2]);
         }
       }
       dft_r<M, true>(za[i]);
       dft_r<M, true>(zb[i]);
     }
   }
-  __syncthreads();
+  wave_sync();   // every lane of the wave has read its row slots
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
     const PairItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      V* row = L.S + it.y * D::PITCH;
 #pragma unroll
       for (int n1 = 0; n1 < M; ++n1) {
-        row[M * it.ma + n1] = za[i][n1];
-        row[M * it.mb + n1] = zb[i][n1];
+        L.S[sidx(it.y, M * it.ma + n1, P)] = za[i][n1];
+        L.S[sidx(it.y, M * it.mb + n1, P)] = zb[i][n1];
       }
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
     const RowItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      const V* row = L.S + it.y * D::PITCH;
       V a[R0];
 #pragma unroll
-      for (int k = 0; k < R0; ++k) a[k] = row[it.n1 + M * k];
-      if constexpr (M > 1) stage_twiddle<R0, true>(a, L.twx, it.n1);
+      for (int k = 0; k < R0; ++k) a[k] = L.S[sidx(it.y, it.n1 + M * k, P)];
+      if constexpr (M > 1) stage_twiddle<R0, M, true>(a, L.twx, it.n1);
       dft_r<R0, true>(a);
 #pragma unroll
       for (int m = 0; m < R0; ++m) out[i][m] = narrow(a[m]);
@@ -413,73 +481,81 @@ __device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L,
 }
 
 // Packed real pairs in the register layout -> forward x transform -> rows
-// S[y][kx] (natural kx, X[0..MX]). The first stage writes the LDS slots the
-// same thread read in x_inverse_to_regs, so no barrier is needed before it.
+// (natural kx, X[0..MX]); ends with a workgroup barrier (the y pass reads
+// columns). The first stage writes the LDS slots the same thread read in
+// x_inverse_to_regs, so no barrier is needed before it; otherwise the caller syncs.
 template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L,
-                                                    const RealRegs<NX, NY, NZ>& in,
+__device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, const RealRegs<NX, NY, NZ>& in,
                                                     int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX;
+  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX, P = D::PITCH;
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
     const RowItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      V* row = L.S + it.y * D::PITCH;
       V a[R0];
 #pragma unroll
       for (int m = 0; m < R0; ++m) a[m] = widen<V>(in[i][m]);
       dft_r<R0, false>(a);
-      if constexpr (M > 1) stage_twiddle<R0, false>(a, L.twx, it.n1);
+      if constexpr (M > 1) stage_twiddle<R0, M, false>(a, L.twx, it.n1);
 #pragma unroll
-      for (int k = 0; k < R0; ++k) row[it.n1 + M * k] = a[k];
+      for (int k = 0; k < R0; ++k) L.S[sidx(it.y, it.n1 + M * k, P)] = a[k];
     }
   }
-  __syncthreads();
+  wave_sync();
   V xa[D::IXP][M], xb[D::IXP][M], xm[D::IXP];
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
     const PairItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      const V* row = L.S + it.y * D::PITCH;
       V za[M], zb[M];
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
-        za[k1] = row[M * it.ma + k1];
-        zb[k1] = row[M * it.mb + k1];
+        za[k1] = L.S[sidx(it.y, M * it.ma + k1, P)];
+        zb[k1] = L.S[sidx(it.y, M * it.mb + k1, P)];
       }
       dft_r<M, false>(za);
       dft_r<M, false>(zb);
-      SplitTwiddle<R0, V> wa(L.twn, it.ma), wb(L.twn, it.mb);
-      // partner Z[MX - k]; for k = 0 it is Z[MX] = Z[0]
+      const V* wa = L.twn + it.ma;   // w^k for k = ma + R0 k1 at wa[R0 k1]
+      const V* wb = L.twn + it.mb;
+      // partner Z[MX - k] (for k = 0 it is Z[MX] = Z[0]), two at a time as above
+      xm[i] = mkc<V>(za[0].x - za[0].y, (typename ScalarOf<V>::T)0);
       if (it.g != 0) {
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) {
-          xa[i][k1] = split_fwd(za[k1], zb[M - 1 - k1], wa.at(k1));
-          xb[i][k1] = split_fwd(zb[k1], za[M - 1 - k1], wb.at(k1));
+          const V a = za[k1], b = zb[M - 1 - k1];
+          xa[i][k1] = split_fwd(a, b, wa[R0 * k1]);
+          xb[i][M - 1 - k1] = split_fwd(b, a, wb[R0 * (M - 1 - k1)]);
         }
       } else {
 #pragma unroll
-        for (int k1 = 0; k1 < M; ++k1) {
-          xa[i][k1] = split_fwd(za[k1], za[(M - k1) % M], wa.at(k1));
-          xb[i][k1] = split_fwd(zb[k1], zb[M - 1 - k1], wb.at(k1));
+        for (int k1 = 0; k1 <= M / 2; ++k1) {
+          const int k2 = (M - k1) % M;
+          const V a = za[k1], b = za[k2];
+          xa[i][k1] = split_fwd(a, b, wa[R0 * k1]);
+          if (k2 != k1) xa[i][k2] = split_fwd(b, a, wa[R0 * k2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < (M + 1) / 2; ++k1) {
+          const int k2 = M - 1 - k1;
+          const V a = zb[k1], b = zb[k2];
+          xb[i][k1] = split_fwd(a, b, wb[R0 * k1]);
+          if (k2 != k1) xb[i][k2] = split_fwd(b, a, wb[R0 * k2]);
         }
       }
-      xm[i] = mkc<V>(za[0].x - za[0].y, (typename ScalarOf<V>::T)0);
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
     const PairItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
-      V* row = L.S + it.y * D::PITCH;
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
-        row[it.ma + R0 * k1] = xa[i][k1];
-        row[it.mb + R0 * k1] = xb[i][k1];
+        L.S[sidx(it.y, it.ma + R0 * k1, P)] = xa[i][k1];
+        L.S[sidx(it.y, it.mb + R0 * k1, P)] = xb[i][k1];
       }
-      if (it.g == 0) row[MX] = xm[i];
+      if (it.g == 0) L.S[sidx(it.y, MX, P)] = xm[i];
     }
   }
   __syncthreads();
@@ -495,7 +571,7 @@ struct PencilLds {
   using Sc = typename ScalarOf<V>::T;
   using D = Dims<NX, NY, NZ>;
   V T[NB][NZ * D::TY];
-  V twz[NZ];
+  V twz[NZ];   // z stage-0 twiddles, transposed table
   Sc hz[NZ];
   V mz[NZ];
   Sc hy[D::TY];
@@ -512,10 +588,8 @@ __device__ __forceinline__ void load_pencil_tables(PencilLds<NX, NY, NZ, V, NB>&
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
   const auto& T = TabSel<V>::get(t);
-  for (int i = tid; i < NZ; i += kThreadsZ) {
-    L.twz[i] = T.tw_z[i];
-    L.hz[i] = T.hz[i];
-  }
+  fill_stage_table<D::RZ0, D::MZB, V, kThreadsZ>(L.twz, T.tw_z, tid);
+  for (int i = tid; i < NZ; i += kThreadsZ) L.hz[i] = T.hz[i];
   if (mz) {
     for (int i = tid; i < NZ; i += kThreadsZ) L.mz[i] = mz[i];
   } else {
@@ -528,26 +602,42 @@ __device__ __forceinline__ void load_pencil_tables(PencilLds<NX, NY, NZ, V, NB>&
   }
 }
 
+// z stage-0 twiddles: FP64 builds the powers in registers (a table read per
+// power would keep 15 complex doubles live next to the butterfly), FP32 reads them.
+template <int R, int M, bool INV, typename V>
+__device__ __forceinline__ void pencil_twiddle(V* a, const V* twT, int n1) {
+  if constexpr (std::is_same<V, double2>::value) stage_twiddle_pow<R, M, INV>(a, twT, n1);
+  else stage_twiddle<R, M, INV>(a, twT, n1);
+}
+
 // Global loads of a tile in the stage-0 butterfly layout: slot i of a thread is
 // item b = tid + i * kThreadsZ, column b % TY, offset n1 = b / TY; value m is z = n1 + MZB m.
 template <int NX, int NY, int NZ>
 __device__ __forceinline__ void z_load(ZRegs<NX, NY, NZ>& r,
                                        const float2* __restrict__ H, int kx, int p0, int tid) {
   using D = Dims<NX, NY, NZ>;
+  constexpr unsigned ZS = D::NKX * NY;   // float2 stride between z planes
 #pragma unroll
   for (int i = 0; i < D::IZ0; ++i) {
     const int b = tid + i * kThreadsZ;
     if (b < D::NZ0) {
       const int col = b % D::TY, n1 = b / D::TY;
+      // wave-uniform base per value (scalar registers) plus one 32-bit lane byte offset
+      const unsigned boff = ((unsigned)n1 * ZS + (unsigned)(kx * NY + p0 + col)) * 8u;
 #pragma unroll
-      for (int m = 0; m < D::RZ0; ++m) r[i][m] = H[((size_t)(n1 + D::MZB * m) * D::NKX + kx) * NY + p0 + col];
+      for (int m = 0; m < D::RZ0; ++m)
+        r[i][m] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(H + (size_t)(D::MZB * m) * ZS) + boff);
     }
   }
 }
 
-// Forward stage 0 of the loaded tile into T.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void z_fwd0(V* T, const ZRegs<NX, NY, NZ>& r,
+// Forward stage 0 of the loaded tile into T (values loaded as float2, or
+// already in the arithmetic type).
+template <typename V> __device__ __forceinline__ V as_arith(float2 v) { return widen<V>(v); }
+template <typename V> __device__ __forceinline__ V as_arith(V v) { return v; }
+
+template <int NX, int NY, int NZ, typename V, typename In>
+__device__ __forceinline__ void z_fwd0(V* T, const In (&r)[Dims<NX, NY, NZ>::IZ0][Dims<NX, NY, NZ>::RZ0],
                                        const V* twz, int tid) {
   using D = Dims<NX, NY, NZ>;
   constexpr int R0 = D::RZ0, M = D::MZB;
@@ -558,9 +648,9 @@ __device__ __forceinline__ void z_fwd0(V* T, const ZRegs<NX, NY, NZ>& r,
       const int col = b % D::TY, n1 = b / D::TY;
       V a[R0];
 #pragma unroll
-      for (int m = 0; m < R0; ++m) a[m] = widen<V>(r[i][m]);
+      for (int m = 0; m < R0; ++m) a[m] = as_arith<V>(r[i][m]);
       dft_r<R0, false>(a);
-      if constexpr (M > 1) stage_twiddle<R0, false>(a, twz, n1);
+      if constexpr (M > 1) pencil_twiddle<R0, M, false>(a, twz, n1);
 #pragma unroll
       for (int k = 0; k < R0; ++k) T[(n1 + M * k) * D::TY + col] = a[k];
     }
@@ -616,10 +706,13 @@ __device__ __forceinline__ void z_inv0_store(const V* T, float2* __restrict__ H,
       V a[R0];
 #pragma unroll
       for (int k = 0; k < R0; ++k) a[k] = T[(n1 + M * k) * D::TY + col];
-      if constexpr (M > 1) stage_twiddle<R0, true>(a, twz, n1);
+      if constexpr (M > 1) pencil_twiddle<R0, M, true>(a, twz, n1);
       dft_r<R0, true>(a);
+      constexpr unsigned ZS = D::NKX * NY;
+      const unsigned boff = ((unsigned)n1 * ZS + (unsigned)(kx * NY + p0 + col)) * 8u;
 #pragma unroll
-      for (int m = 0; m < R0; ++m) H[((size_t)(n1 + M * m) * D::NKX + kx) * NY + p0 + col] = narrow(a[m]);
+      for (int m = 0; m < R0; ++m)
+        *reinterpret_cast<float2*>(reinterpret_cast<char*>(H + (size_t)(M * m) * ZS) + boff) = narrow(a[m]);
     }
   }
 }
@@ -667,7 +760,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restri
   }
   __syncthreads();
   x_forward_from_regs(L, v, tid);
-  y_forward_to_global(L, B.spec[0] + (size_t)z * D::SLAB_C, tid);
+  y_forward_to_global(L, B.spec[0] + (size_t)z * D::SLAB_C, TabSel<V>::get(t).tw_y, tid);
 }
 
 // Pencil pass of the gradient: in = FFT_xy(p) (overwritten by Q), out2 = Gz, with
@@ -679,7 +772,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, flo
                                                      WaveTables t, float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
-  __shared__ PencilLds<NX, NY, NZ, V, 2> L;
+  __shared__ PencilLds<NX, NY, NZ, V, 1> L;   // one tile buffer: Q and Gz leave one after the other
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
@@ -706,10 +799,12 @@ __global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, flo
     }
   }
   z_inv1<NX, NY, NZ>(L.T[0], v, tid);
-  z_inv1<NX, NY, NZ>(L.T[1], w, tid);
   __syncthreads();
   z_inv0_store<NX, NY, NZ>(L.T[0], P, kx, p0, L.twz, tid);
-  z_inv0_store<NX, NY, NZ>(L.T[1], Gz, kx, p0, L.twz, tid);
+  __syncthreads();
+  z_inv1<NX, NY, NZ>(L.T[0], w, tid);
+  __syncthreads();
+  z_inv0_store<NX, NY, NZ>(L.T[0], Gz, kx, p0, L.twz, tid);
 }
 
 // Pencil pass applying kappa/N times i k_xi exp(s i k_xi dx/2) (PLUS: s = +1,
@@ -773,7 +868,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
                    xi == 0 ? tab.mpx : (xi == 1 ? tab.mpy : (const V*)nullptr), xi == 2 ? 0 : xi + 1, tid);
   const float azz = t.az[z];
   __syncthreads();
-  y_inverse_from_global(L, (xi == 2 ? Gz : Q) + cz, xi == 2 ? 0 : xi + 1, tid);
+  y_inverse_from_global(L, (xi == 2 ? Gz : Q) + cz, xi == 2 ? 0 : xi + 1, TabSel<V>::get(t).tw_y, tid);
   float2 g[D::IX0][D::RX0];
   x_inverse_to_regs(L, g, tid);
 #pragma unroll
@@ -798,7 +893,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
   }
   x_forward_from_regs(L, g, tid);
   float2* U = xi == 0 ? U0 : (xi == 1 ? U1 : U2);
-  y_forward_to_global(L, U + cz, tid);
+  y_forward_to_global(L, U + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // Density update of all three components of slab z, p = c0^2 sum rho, sensor
@@ -827,7 +922,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restri
     int tl = tid;
     asm volatile("" : "+v"(tl));
     __syncthreads();   // tables (first pass) / previous pass done with S
-    y_inverse_from_global(L, H + cz, 0, tl);
+    y_inverse_from_global(L, H + cz, 0, TabSel<V>::get(t).tw_y, tl);
     float2 ro[D::IX0][D::RX0];
     load_real<NX, NY, NZ>(ro, r, tl);   // in flight during the x pass
     float2 h[D::IX0][D::RX0];
@@ -866,7 +961,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restri
     }
   }
   x_forward_from_regs(L, p, tid);
-  y_forward_to_global(L, Pout + cz, tid);
+  y_forward_to_global(L, Pout + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // ---- adjoint kernels ---------------------------------------------------------
@@ -914,7 +1009,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_init(const float* __restri
     }
   }
   x_forward_from_regs(L, v, tid);
-  y_forward_to_global(L, B.spec[xi] + cz, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // u^_xi: uh = u^ + dt rho0 Dplus_xi(b rho^) (the pencil pass already applied the
@@ -933,7 +1028,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTable
   load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, (const V*)nullptr, 0, tid);
   const float azz = t.az[z];
   __syncthreads();
-  y_inverse_from_global(L, B.spec[xi] + cz, 0, tid);
+  y_inverse_from_global(L, B.spec[xi] + cz, 0, TabSel<V>::get(t).tw_y, tid);
   float2 g[D::IX0][D::RX0];
   x_inverse_to_regs(L, g, tid);
 #pragma unroll
@@ -954,7 +1049,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTable
     }
   }
   x_forward_from_regs(L, g, tid);
-  y_forward_to_global(L, B.spec[xi] + cz, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // Pencil pass of the summed divergence: out = IFFT_z[ sum_xi kappa/N i k_xi
@@ -965,62 +1060,57 @@ __global__ __launch_bounds__(kThreadsZ) void k_zdiv_sum(const float2* __restrict
                                                         const float2* __restrict__ W2,
                                                         float2* __restrict__ out, WaveTables t,
                                                         float inv_ntot) {
+  // The x and y factors do not depend on kz, so they are applied before the z
+  // transform: out = IFFT_z[ kappa/N ( FFT_z(mx W0 + my W1) + mz FFT_z(W2) ) ],
+  // two forward transforms instead of three.
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
   __shared__ PencilLds<NX, NY, NZ, V, 1> L;
-  __shared__ V fy[3][D::TY];   // per component: the x or y factor by column (else 1)
-  __shared__ V fz[3][NZ];      // per component: the z factor by kz position (else 1)
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
-  float2 r[D::IZ0][D::RZ0];
-  z_load<NX, NY, NZ>(r, W0, kx, p0, tid);
-  const V one = mkc<V>((Sc)1, (Sc)0);
-  load_pencil_tables(L, t, p0, one, (const V*)nullptr, (const V*)nullptr, tid);
-  for (int i = tid; i < NZ; i += kThreadsZ) {
-    fz[0][i] = one;
-    fz[1][i] = one;
-    fz[2][i] = tab.mmz[i];
-  }
-  if (tid < D::TY) {
-    fy[0][tid] = tab.mmx[kx];
-    fy[1][tid] = tab.mmy[p0 + tid];
-    fy[2][tid] = one;
-  }
+  float2 r0[D::IZ0][D::RZ0], r1[D::IZ0][D::RZ0];
+  z_load<NX, NY, NZ>(r0, W0, kx, p0, tid);
+  z_load<NX, NY, NZ>(r1, W1, kx, p0, tid);
+  load_pencil_tables(L, t, p0, mkc<V>((Sc)1, (Sc)0), tab.mmy, tab.mmz, tid);
   const Sc hx = tab.hx[kx];
+  const V mxk = tab.mmx[kx];
   __syncthreads();
-  // kappa is common to the three terms: sum m_xi FFT_z(W_xi) first, scale once
-  V acc[D::IZ1][D::MZB];
+  {
+    V a[D::IZ0][D::RZ0];
 #pragma unroll
-  for (int i = 0; i < D::IZ1; ++i)
+    for (int i = 0; i < D::IZ0; ++i) {
+      const int b = tid + i * kThreadsZ;
+      const V myc = L.my[b % D::TY];
 #pragma unroll
-    for (int k1 = 0; k1 < D::MZB; ++k1) acc[i][k1] = mkc<V>((Sc)0, (Sc)0);
-#pragma unroll 1
-  for (int xi = 0; xi < 3; ++xi) {
-    int tl = tid;   // opaque copy: addresses are recomputed per component, not kept live
-    asm volatile("" : "+v"(tl));
-    z_fwd0<NX, NY, NZ>(L.T[0], r, L.twz, tl);
-    if (xi < 2) z_load<NX, NY, NZ>(r, xi == 0 ? W1 : W2, kx, p0, tl);   // next component in flight
-    __syncthreads();
-    V v[D::IZ1][D::MZB];
-    z_fwd1<NX, NY, NZ>(L.T[0], v, tl);
-#pragma unroll
-    for (int i = 0; i < D::IZ1; ++i) {
-      const int b = tl + i * kThreadsZ;
-      const int col = b % D::TY, mb = (b / D::TY) % D::RZ0;
-#pragma unroll
-      for (int k1 = 0; k1 < D::MZB; ++k1)
-        acc[i][k1] = cadd(acc[i][k1], cmul(v[i][k1], cmul(fy[xi][col], fz[xi][D::MZB * mb + k1])));
+      for (int m = 0; m < D::RZ0; ++m)
+        a[i][m] = cadd(cmul(mxk, widen<V>(r0[i][m])), cmul(myc, widen<V>(r1[i][m])));
     }
-    __syncthreads();
+    z_fwd0<NX, NY, NZ>(L.T[0], a, L.twz, tid);
   }
+  // W2 in flight during the first transform's second stage (the memory clobber
+  // keeps the loads after the first stage, whose registers they reuse)
+  int tn = tid;
+  asm volatile("" : "+v"(tn)::"memory");
+  z_load<NX, NY, NZ>(r0, W2, kx, p0, tn);
+  __syncthreads();
+  V acc[D::IZ1][D::MZB];
+  z_fwd1<NX, NY, NZ>(L.T[0], acc, tid);
+  __syncthreads();
+  z_fwd0<NX, NY, NZ>(L.T[0], r0, L.twz, tid);
+  __syncthreads();
+  V v[D::IZ1][D::MZB];
+  z_fwd1<NX, NY, NZ>(L.T[0], v, tid);
 #pragma unroll
   for (int i = 0; i < D::IZ1; ++i) {
     const int b = tid + i * kThreadsZ;
     const int col = b % D::TY, mb = (b / D::TY) % D::RZ0;
 #pragma unroll
-    for (int k1 = 0; k1 < D::MZB; ++k1)
-      acc[i][k1] = cscale(acc[i][k1], kappa_n(hx, L.hy[col], L.hz[D::MZB * mb + k1], inv_ntot));
+    for (int k1 = 0; k1 < D::MZB; ++k1) {
+      const int q = D::MZB * mb + k1;
+      acc[i][k1] = cscale(cadd(acc[i][k1], cmul(v[i][k1], L.mz[q])),
+                          kappa_n(hx, L.hy[col], L.hz[q], inv_ntot));
+    }
   }
   z_inv1<NX, NY, NZ>(L.T[0], acc, tid);
   __syncthreads();
@@ -1047,7 +1137,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restri
   load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
   __syncthreads();
-  y_inverse_from_global(L, Qs + cz, 0, tid);
+  y_inverse_from_global(L, Qs + cz, 0, TabSel<V>::get(t).tw_y, tid);
   float2 q[D::IX0][D::RX0];
   x_inverse_to_regs(L, q, tid);
   const float qs = sc.c2 * sc.dt_over_rho0;
@@ -1074,7 +1164,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restri
   // last step: the initial-condition transpose needs R2C(u^) instead (read once per adjoint)
   if (final_step) load_real<NX, NY, NZ>(q, ub, tid);
   x_forward_from_regs(L, q, tid);
-  y_forward_to_global(L, B.spec[xi] + cz, tid);
+  y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // p = (rho^_x + rho^_y + rho^_z)/(3 c0^2) - dt/(2 rho0) sum_xi Dminus_xi u^_xi.
@@ -1090,7 +1180,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __rest
   if (with_velocity) {
     load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
     __syncthreads();
-    y_inverse_from_global(L, Qs + cz, 0, tid);
+    y_inverse_from_global(L, Qs + cz, 0, TabSel<V>::get(t).tw_y, tid);
     x_inverse_to_regs(L, g, tid);
   }
   float2 r0[D::IX0][D::RX0], r1[D::IX0][D::RX0], r2[D::IX0][D::RX0];

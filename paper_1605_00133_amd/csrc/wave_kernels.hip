@@ -48,20 +48,21 @@ constexpr int kThreadsSlab = 512;
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Slot of row index idx in an LDS slab row: an XOR of its low three bits with
-// the next three. Every exchange below then touches 8 distinct 16-byte slots
-// per 8 lanes (together with a row pitch = 4 mod 8), whether lanes run along
-// a row, down a column or over the butterflies of neighbouring rows.
-__host__ __device__ constexpr int slot_of(int idx) { return idx ^ ((idx >> 3) & 7); }
-__host__ __device__ constexpr int slab_pitch(int mx) {   // smallest pitch > slot_of(mx), = 4 mod 8
-  return slot_of(mx) + 1 + ((4 - (slot_of(mx) + 1) % 8) + 8) % 8;
+// Slot of row index idx in an LDS slab row: one pad slot after every 8. With
+// a row pitch = 1 mod 8, 8 lanes that touch 8 consecutive indices of one row,
+// indices 8 apart, or the same index of rows 4 apart hit 8 distinct 16-byte
+// slots, so every exchange below is free of bank conflicts; and for
+// idx = j + 8 k (j < 8) the slot j + 9 k is a constant offset from a per-lane base.
+__host__ __device__ constexpr int slot_of(int idx) { return idx + (idx >> 3); }
+__host__ __device__ constexpr int slab_pitch(int mx) {   // smallest pitch > slot_of(mx), = 1 mod 8
+  return slot_of(mx) + 1 + ((1 - (slot_of(mx) + 1) % 8) + 8) % 8;
 }
 
 template <int NX, int NY, int NZ>
 struct Dims {
   static constexpr int MX = NX / 2;          // complex length of a packed real row
   static constexpr int NKX = MX + 1;         // half-spectrum length
-  static constexpr int PITCH = slab_pitch(MX);   // LDS row pitch (complex), = 4 mod 8
+  static constexpr int PITCH = slab_pitch(MX);   // LDS row pitch (complex), = 1 mod 8
   static constexpr int SLAB_C = NKX * NY;    // complex values per slab spectrum
   static constexpr int SLAB_P = NY * MX;     // float2 pairs per real slab
   // two-stage splits L = R0 * M of the x (packed), y and z transforms
@@ -82,7 +83,7 @@ struct Dims {
   static constexpr int IZ0 = cdiv(NZ0, kThreadsZ), IZ1 = cdiv(NZ1, kThreadsZ);
   static_assert(RX0 >= 4 && RX0 % 2 == 0, "x split needs an even first radix");
   static_assert(NY % NWAVES == 0 || NY < NWAVES, "rows must split evenly over the waves");
-  static_assert(PITCH >= slot_of(MX) + 1 && PITCH % 8 == 4, "slab pitch");
+  static_assert(PITCH >= slot_of(MX) + 1 && PITCH % 8 == 1, "slab pitch");
 };
 
 // Register arrays of the real-space layout (per slot i, value m) and of a pencil tile.
@@ -273,25 +274,37 @@ __device__ __forceinline__ void y_twiddle(V* a, const SlabLds<NX, NY, NZ, V>& L,
   }
 }
 
-// y inverse transform of the slab spectrum g[kx][ky_pos] (times an optional
-// derivative factor L.mul by kx (mode 1) or ky_pos (mode 2)), read straight
-// from HBM into the stage-1 butterflies; leaves the rows in natural y order
-// (index kx). Caller syncs before (tables); ends synced.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void y_inverse_from_global(SlabLds<NX, NY, NZ, V>& L, const float2* __restrict__ g,
-                                                      int mode, const V* __restrict__ twg, int tid) {
+// Registers of the y stage-1 global loads (slot i, value k1).
+template <int NX, int NY, int NZ>
+using YRegs = float2[YItems<NX, NY, NZ>::I1 + 1][Dims<NX, NY, NZ>::MYB];
+
+// Global loads of the slab spectrum g[kx][ky_pos] in the stage-1 butterfly
+// layout; issued before anything else a kernel waits on, so their latency
+// overlaps the table loads and the barrier that follows.
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void y_load(YRegs<NX, NY, NZ>& r, const float2* __restrict__ g, int tid) {
   using D = Dims<NX, NY, NZ>;
   using Y = YItems<NX, NY, NZ>;
-  constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
-  float2 r[Y::I1 + 1][M];
+  constexpr int M = D::MYB;
 #pragma unroll
-  for (int i = 0; i <= Y::I1; ++i) {   // every global load in flight before any arithmetic
+  for (int i = 0; i <= Y::I1; ++i) {
     int kx, mb;
     if (Y::s1(tid, i, kx, mb)) {
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) r[i][k1] = g[kx * NY + M * mb + k1];
     }
   }
+}
+
+// y inverse transform of the loaded slab spectrum (times an optional derivative
+// factor L.mul by kx (mode 1) or ky_pos (mode 2)); leaves the rows in natural
+// y order (index kx). Caller syncs before (tables); ends synced.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void y_inverse(SlabLds<NX, NY, NZ, V>& L, const YRegs<NX, NY, NZ>& r, int mode,
+                                          const V* __restrict__ twg, int tid) {
+  using D = Dims<NX, NY, NZ>;
+  using Y = YItems<NX, NY, NZ>;
+  constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
 #pragma unroll
   for (int i = 0; i <= Y::I1; ++i) {
     int kx, mb;
@@ -395,7 +408,11 @@ struct PairItem {
   __device__ __forceinline__ PairItem(int tid, int i) {
     const int e = (tid & 63) + 64 * i;
     ok = e < D::RPW * D::PPR && (tid >> 6) * D::RPW < NY;
-    y = (tid >> 6) * D::RPW + e / D::PPR;
+    // with 4 pair items per row, the two 4-lane halves of an 8-lane group take
+    // rows 4 apart (r = 2j + h -> row j % 4 + 4 h + 8 (j / 4)), see slot_of()
+    const int r = e / D::PPR;
+    const int rr = (D::PPR == 4 && D::RPW % 8 == 0) ? ((r >> 1) & 3) + 4 * (r & 1) + 8 * (r >> 3) : r;
+    y = (tid >> 6) * D::RPW + rr;
     g = e % D::PPR;
     ma = g;
     mb = g == 0 ? D::RX0 / 2 : D::RX0 - g;
@@ -862,13 +879,15 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
   slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
   float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
+  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+  y_load<NX, NY, NZ>(ry, (xi == 2 ? Gz : Q) + cz, tid);
   float2 uo[D::IX0][D::RX0];
   if (!init) load_real<NX, NY, NZ>(uo, u, tid);   // in flight during the transform
   load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr,
                    xi == 0 ? tab.mpx : (xi == 1 ? tab.mpy : (const V*)nullptr), xi == 2 ? 0 : xi + 1, tid);
   const float azz = t.az[z];
   __syncthreads();
-  y_inverse_from_global(L, (xi == 2 ? Gz : Q) + cz, xi == 2 ? 0 : xi + 1, TabSel<V>::get(t).tw_y, tid);
+  y_inverse(L, ry, xi == 2 ? 0 : xi + 1, TabSel<V>::get(t).tw_y, tid);
   float2 g[D::IX0][D::RX0];
   x_inverse_to_regs(L, g, tid);
 #pragma unroll
@@ -921,8 +940,10 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restri
     // passes are recomputed per component instead of being kept live across the loop
     int tl = tid;
     asm volatile("" : "+v"(tl));
+    float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+    y_load<NX, NY, NZ>(ry, H + cz, tl);
     __syncthreads();   // tables (first pass) / previous pass done with S
-    y_inverse_from_global(L, H + cz, 0, TabSel<V>::get(t).tw_y, tl);
+    y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tl);
     float2 ro[D::IX0][D::RX0];
     load_real<NX, NY, NZ>(ro, r, tl);   // in flight during the x pass
     float2 h[D::IX0][D::RX0];
@@ -1023,12 +1044,14 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTable
   slab_field_of_block(blockIdx.x, z, xi);
   const size_t cz = (size_t)z * D::SLAB_C;
   float2* ub = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
+  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+  y_load<NX, NY, NZ>(ry, B.spec[xi] + cz, tid);
   float2 uo[D::IX0][D::RX0];
   load_real<NX, NY, NZ>(uo, ub, tid);
   load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, (const V*)nullptr, 0, tid);
   const float azz = t.az[z];
   __syncthreads();
-  y_inverse_from_global(L, B.spec[xi] + cz, 0, TabSel<V>::get(t).tw_y, tid);
+  y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
   float2 g[D::IX0][D::RX0];
   x_inverse_to_regs(L, g, tid);
 #pragma unroll
@@ -1131,13 +1154,15 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restri
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
   float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
   const float2* ub = reinterpret_cast<const float2*>(B.u[xi]) + rz;
+  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+  y_load<NX, NY, NZ>(ry, Qs + cz, tid);
   float2 ro[D::IX0][D::RX0], src[D::IX0][D::RX0];
   load_real<NX, NY, NZ>(ro, rb, tid);
   if (z == 0) load_real<NX, NY, NZ>(src, reinterpret_cast<const float2*>(yplane), tid);   // data source
   load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
   __syncthreads();
-  y_inverse_from_global(L, Qs + cz, 0, TabSel<V>::get(t).tw_y, tid);
+  y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
   float2 q[D::IX0][D::RX0];
   x_inverse_to_regs(L, q, tid);
   const float qs = sc.c2 * sc.dt_over_rho0;
@@ -1178,9 +1203,11 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __rest
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
   float2 g[D::IX0][D::RX0];
   if (with_velocity) {
+    float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+    y_load<NX, NY, NZ>(ry, Qs + cz, tid);
     load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
     __syncthreads();
-    y_inverse_from_global(L, Qs + cz, 0, TabSel<V>::get(t).tw_y, tid);
+    y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
     x_inverse_to_regs(L, g, tid);
   }
   float2 r0[D::IX0][D::RX0], r1[D::IX0][D::RX0], r2[D::IX0][D::RX0];

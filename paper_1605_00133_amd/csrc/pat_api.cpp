@@ -39,7 +39,7 @@ constexpr int kRedSlots = 16;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u[3], rho[3], spec[4], planes, red_partial, red_out;
+  size_t u[3], rho[3], spec[4], planes2, planes, red_partial, red_out;
   size_t img[7], dual, data[6];
   size_t total;
 };
@@ -63,6 +63,7 @@ Layout make_layout(const pat_grid& g, const pat_sampling& s) {
   for (int i = 0; i < 3; ++i) L.u[i] = take(R);
   for (int i = 0; i < 3; ++i) L.rho[i] = take(R);
   for (int i = 0; i < 4; ++i) L.spec[i] = take(C);
+  L.planes2 = take(2 * (size_t)g.nt * n_pix(g) * sizeof(float));
   L.planes = s.kind == PAT_SAMPLE_FULL ? 0 : take((size_t)g.nt * n_pix(g) * sizeof(float));
   L.red_partial = take(kRedBlocks * sizeof(double));
   L.red_out = take(kRedSlots * sizeof(double));
@@ -183,6 +184,7 @@ struct pat_plan {
   char* ws;
   Layout L;
   WaveBuffers wb;
+  float* planes2;           // the two sensor-plane series of the forward propagation
   float* planes;
   double* red_partial;
   double* red_out;
@@ -333,8 +335,10 @@ long data_n(const pat_plan* P) { return (long)P->g.nt * P->mc; }
 // ---- operator pieces used by the entry points and the solver ----------------
 pat_status op_forward(pat_plan* P, const float* p0, float* f) {
   float* planes = P->kind == PAT_SAMPLE_FULL ? f : P->planes;
-  PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, planes, P->g.nt, P->stream,
+  const long nplane = (long)P->g.nt * P->npix;
+  PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, P->planes2, P->g.nt, P->stream,
                                P->timer.ev ? &P->timer : nullptr));
+  PAT_TRY_HIP(launch_sum2(P->planes2, nplane, planes, nplane, P->stream));
   if (P->kind == PAT_SAMPLE_POINTS)
     PAT_TRY_HIP(launch_rsp_gather(planes, P->idx, f, P->npix, P->mc, P->g.nt, P->stream));
   else if (P->kind == PAT_SAMPLE_HADAMARD)
@@ -468,6 +472,7 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
     P->wb.rho[i] = ws_ptr<float>(P, L.rho[i]);
   }
   for (int i = 0; i < 4; ++i) P->wb.spec[i] = ws_ptr<float2>(P, L.spec[i]);
+  P->planes2 = ws_ptr<float>(P, L.planes2);
   P->planes = smp->kind == PAT_SAMPLE_FULL ? nullptr : ws_ptr<float>(P, L.planes);
   P->red_partial = ws_ptr<double>(P, L.red_partial);
   P->red_out = ws_ptr<double>(P, L.red_out);
@@ -790,7 +795,7 @@ pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char**
   static const char* kNames[K_COUNT] = {"k_zgrad", "k_fwd_u", "k_zmul<div>", "k_fwd_rho",
                                         "k_zmul<grad>", "k_adj_u", "k_zdiv_sum", "k_adj_rho"};
   // algorithmic HBM bytes per launch in units of C (one slab-spectrum field) and R (one real field)
-  static const int kC[K_COUNT] = {3, 5, 6, 4, 6, 6, 4, 4};
+  static const int kC[K_COUNT] = {4, 5, 6, 5, 6, 6, 4, 4};
   static const int kR[K_COUNT] = {0, 6, 0, 6, 0, 6, 0, 6};
   PAT_TRY(check_plan(plan));
   if (kernel_id < 0 || kernel_id >= K_COUNT) return set_error(PAT_ERR_INVALID, "pat_kernel_info: bad kernel_id");

@@ -21,6 +21,8 @@ hipError_t launch_psnr(const float* a, const float* b, int nx, int ny, int nz, i
 hipError_t launch_extrapolate(const float* x, const float* xp, float* out, float beta, long n, hipStream_t st);
 hipError_t launch_axpy(const float* a, const float* b, float* out, float s, long n, hipStream_t st);
 hipError_t launch_scale(const float* a, float* out, float s, long n, hipStream_t st);
+// out[i] = a[i] + a[i + stride], i < n
+hipError_t launch_sum2(const float* a, long stride, float* out, long n, hipStream_t st);
 hipError_t launch_fill(float* out, float v, long n, hipStream_t st);
 
 }  // namespace pat

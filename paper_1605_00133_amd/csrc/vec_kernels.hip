@@ -267,6 +267,13 @@ __global__ __launch_bounds__(kThreadsVec) void k_scale(const float* __restrict__
   if (i < n) out[i] = s * a[i];
 }
 
+// out = a + a[stride] (two plane series)
+__global__ __launch_bounds__(kThreadsVec) void k_sum2(const float* __restrict__ a, long stride,
+                                                      float* __restrict__ out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + a[i + stride];
+}
+
 __global__ __launch_bounds__(kThreadsVec) void k_fill(float* __restrict__ out, float v, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = v;
@@ -351,6 +358,12 @@ hipError_t launch_axpy(const float* a, const float* b, float* out, float s, long
 hipError_t launch_scale(const float* a, float* out, float s, long n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   k_scale<<<nblocks(n), kThreadsVec, 0, st>>>(a, out, s, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum2(const float* a, long stride, float* out, long n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_sum2<<<nblocks(n), kThreadsVec, 0, st>>>(a, stride, out, n);
   return hipGetLastError();
 }
 

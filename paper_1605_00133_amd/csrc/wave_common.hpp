@@ -59,14 +59,14 @@ struct WaveBuffers {
 
 // Kernels of one time step, for per-kernel timing.
 enum KernelId {
-  K_ZGRAD = 0,      // forward pencil pass of the gradient (1 spectrum in, 2 out)
+  K_ZGRAD = 0,      // forward pencil pass of the gradient (2 spectra in, 2 out)
   K_FWD_U = 1,      // forward slab pass: velocity update + R2C (per component)
   K_ZDIV = 2,       // forward pencil pass of the divergences (per component)
-  K_FWD_RHO = 3,    // forward slab pass: density update, p, sensor plane, R2C of p
+  K_FWD_RHO = 3,    // forward slab pass: density update, sensor plane, R2C (two halves per slab)
   K_ZGRAD_ADJ = 4,  // adjoint pencil pass of the gradients (per component)
   K_ADJ_U = 5,      // adjoint slab pass: velocity update + R2C (per component)
   K_ZDIV_SUM = 6,   // adjoint pencil pass of the summed divergence (3 in, 1 out)
-  K_ADJ_RHO = 7,    // adjoint slab pass: density update + source + R2C (per component)
+  K_ADJ_RHO = 7,    // adjoint slab pass: density update + source + R2C (two halves per slab)
   K_COUNT = 8
 };
 
@@ -79,8 +79,10 @@ struct KernelTimer {
   int count;
 };
 
+// Forward: planes receives two sensor-plane series, [2][nt][ny][nx] (the two
+// halves of the density pass); their sum is p on the plane z = 0.
 using WaveLaunchFwd = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
-                                     const float* p0, float* planes, int nt, hipStream_t, KernelTimer*);
+                                     const float* p0, float* planes2, int nt, hipStream_t, KernelTimer*);
 using WaveLaunchAdj = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
                                      const float* planes, float* p, int nt, hipStream_t, KernelTimer*);
 

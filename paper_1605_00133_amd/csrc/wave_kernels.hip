@@ -750,11 +750,12 @@ __device__ __forceinline__ void slab_field_of_block(int b, int& z, int& xi) {
 
 // ---- forward kernels ---------------------------------------------------------
 
-// rho_xi = p0 / (3 c0^2); plane 0 = p0[z = 0]; spec0 = slab R2C of p0.
+// rho_xi = p0 / (3 c0^2); sensor plane 0 = p0[z = 0] in the first of the two
+// plane series (plane_b, the second, starts at 0); spec0 = slab R2C of p0.
 template <int NX, int NY, int NZ, typename V>
 __global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restrict__ p0, WaveBuffers B,
-                                                           float* __restrict__ plane0, WaveTables t,
-                                                           WaveScalars sc) {
+                                                           float* __restrict__ plane0, float* __restrict__ plane_b,
+                                                           WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int z = blockIdx.x, tid = threadIdx.x;
@@ -771,7 +772,10 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restri
         const float2 r = make_float2(v[i][m].x * sc.inv_3c2, v[i][m].y * sc.inv_3c2);
 #pragma unroll
         for (int xi = 0; xi < 3; ++xi) reinterpret_cast<float2*>(B.rho[xi])[off + it.pair(m)] = r;
-        if (z == 0) reinterpret_cast<float2*>(plane0)[it.pair(m)] = v[i][m];
+        if (z == 0) {
+          reinterpret_cast<float2*>(plane0)[it.pair(m)] = v[i][m];
+          reinterpret_cast<float2*>(plane_b)[it.pair(m)] = make_float2(0.f, 0.f);
+        }
       }
     }
   }
@@ -780,24 +784,33 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restri
   y_forward_to_global(L, B.spec[0] + (size_t)z * D::SLAB_C, TabSel<V>::get(t).tw_y, tid);
 }
 
-// Pencil pass of the gradient: in = FFT_xy(p) (overwritten by Q), out2 = Gz, with
+// Pencil pass of the gradient: in = FFT_xy(p) = P0 (+ P1 when nin = 2; the two
+// halves of the density pass), out Q and Gz with
 // Q = IFFT_z[kappa FFT_z(in)] / N and Gz = IFFT_z[kappa i kz e^{i kz dx/2} FFT_z(in)] / N.
 // The x and y derivative factors are applied later in the slab kernel (they
 // depend only on kx or ky_pos), so one input yields two outputs instead of three.
+// Qo may alias P0 and Gz P1: a tile reads all its inputs before it writes.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, float2* __restrict__ Gz,
-                                                     WaveTables t, float inv_ntot) {
+__global__ __launch_bounds__(kThreadsZ) void k_zgrad(const float2* P0, const float2* P1, int nin, float2* Qo,
+                                                     float2* Gz, WaveTables t, float inv_ntot) {
   using D = Dims<NX, NY, NZ>;
   using Sc = typename ScalarOf<V>::T;
   __shared__ PencilLds<NX, NY, NZ, V, 1> L;   // one tile buffer: Q and Gz leave one after the other
   const auto& tab = TabSel<V>::get(t);
   const int tid = threadIdx.x;
   const int kx = blockIdx.x / (NY / D::TY), p0 = (blockIdx.x % (NY / D::TY)) * D::TY;
-  float2 r[D::IZ0][D::RZ0];
-  z_load<NX, NY, NZ>(r, P, kx, p0, tid);
+  float2 r[D::IZ0][D::RZ0], r1[D::IZ0][D::RZ0];
+  z_load<NX, NY, NZ>(r, P0, kx, p0, tid);
+  if (nin > 1) z_load<NX, NY, NZ>(r1, P1, kx, p0, tid);
   load_pencil_tables(L, t, p0, mkc<V>((Sc)1, (Sc)0), (const V*)nullptr, tab.mpz, tid);
   const Sc hx = tab.hx[kx];
   __syncthreads();
+  if (nin > 1) {   // the sum is formed in FP32, like the stored spectra it adds up
+#pragma unroll
+    for (int i = 0; i < D::IZ0; ++i)
+#pragma unroll
+      for (int m = 0; m < D::RZ0; ++m) r[i][m] = make_float2(r[i][m].x + r1[i][m].x, r[i][m].y + r1[i][m].y);
+  }
   z_fwd0<NX, NY, NZ>(L.T[0], r, L.twz, tid);
   __syncthreads();
   V v[D::IZ1][D::MZB], w[D::IZ1][D::MZB];
@@ -817,7 +830,7 @@ __global__ __launch_bounds__(kThreadsZ) void k_zgrad(float2* __restrict__ P, flo
   }
   z_inv1<NX, NY, NZ>(L.T[0], v, tid);
   __syncthreads();
-  z_inv0_store<NX, NY, NZ>(L.T[0], P, kx, p0, L.twz, tid);
+  z_inv0_store<NX, NY, NZ>(L.T[0], Qo, kx, p0, L.twz, tid);
   __syncthreads();
   z_inv1<NX, NY, NZ>(L.T[0], w, tid);
   __syncthreads();
@@ -915,25 +928,29 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
   y_forward_to_global(L, U + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
-// Density update of all three components of slab z, p = c0^2 sum rho, sensor
-// plane, and R2C of p into Pout. The sum is formed from the new components as
-// stored (each thread re-reads its own values), which keeps the three
-// transforms free of a live accumulator.
+// Density update of slab z = blockIdx.x / 2. The slab's work is split over two
+// blocks so that 2 nz blocks of at most three 2D transforms replace nz blocks
+// of four: block half 0 updates rho_x, rho_y and writes Pa = R2C(c0^2 (rho_x +
+// rho_y)); half 1 updates rho_z and writes Pb = R2C(c0^2 rho_z). The pencil pass
+// of the gradient sums Pa + Pb = FFT_xy(p), p = c0^2 sum rho; the sensor plane
+// contributions go to plane_a / plane_b (summed after the run). The sums are
+// formed from the new components as stored (each thread re-reads its own
+// values), which keeps the transforms free of a live accumulator.
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restrict__ H0,
-                                                          const float2* __restrict__ H1,
-                                                          const float2* __restrict__ H2, WaveBuffers B,
-                                                          float2* __restrict__ Pout,
-                                                          float* __restrict__ plane, WaveTables t,
-                                                          WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* H0, const float2* H1, const float2* H2,
+                                                          WaveBuffers B, float2* Pa, float2* Pb,
+                                                          float* __restrict__ plane_a, float* __restrict__ plane_b,
+                                                          WaveTables t, WaveScalars sc) {
   using D = Dims<NX, NY, NZ>;
   __shared__ SlabLds<NX, NY, NZ, V> L;
-  const int z = blockIdx.x, tid = threadIdx.x;
+  const int z = blockIdx.x >> 1, half = blockIdx.x & 1, tid = threadIdx.x;
+  const int xi0 = half == 0 ? 0 : 2, nxi = half == 0 ? 2 : 1;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  load_slab_tables(L, t, t.bx, t.by, (const V*)nullptr, 0, tid);
+  load_slab_tables(L, t, half == 0 ? t.bx : nullptr, half == 0 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
 #pragma unroll 1
-  for (int xi = 0; xi < 3; ++xi) {
+  for (int c = 0; c < nxi; ++c) {
+    const int xi = xi0 + c;
     const float2* H = xi == 0 ? H0 : (xi == 1 ? H1 : H2);
     float2* r = reinterpret_cast<float2*>(B.rho[xi]) + rz;
     // an opaque copy of the thread index: the LDS and global addresses of the
@@ -965,24 +982,25 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* __restri
       }
     }
   }
-  float2 p[D::IX0][D::RX0], r1[D::IX0][D::RX0], r2[D::IX0][D::RX0];
-  load_real<NX, NY, NZ>(p, reinterpret_cast<const float2*>(B.rho[0]) + rz, tid);
-  load_real<NX, NY, NZ>(r1, reinterpret_cast<const float2*>(B.rho[1]) + rz, tid);
-  load_real<NX, NY, NZ>(r2, reinterpret_cast<const float2*>(B.rho[2]) + rz, tid);
+  float2 p[D::IX0][D::RX0], r1[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(p, reinterpret_cast<const float2*>(B.rho[xi0]) + rz, tid);
+  if (nxi == 2) load_real<NX, NY, NZ>(r1, reinterpret_cast<const float2*>(B.rho[1]) + rz, tid);
+  float* plane = half == 0 ? plane_a : plane_b;
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
     const RowItem<NX, NY, NZ> it(tid, i);
     if (it.ok) {
 #pragma unroll
       for (int m = 0; m < D::RX0; ++m) {
-        p[i][m] = make_float2((p[i][m].x + r1[i][m].x + r2[i][m].x) * sc.c2,
-                              (p[i][m].y + r1[i][m].y + r2[i][m].y) * sc.c2);
+        float2 v = p[i][m];
+        if (nxi == 2) v = make_float2(v.x + r1[i][m].x, v.y + r1[i][m].y);
+        p[i][m] = make_float2(v.x * sc.c2, v.y * sc.c2);
         if (z == 0) reinterpret_cast<float2*>(plane)[it.pair(m)] = p[i][m];
       }
     }
   }
   x_forward_from_regs(L, p, tid);
-  y_forward_to_global(L, Pout + cz, TabSel<V>::get(t).tw_y, tid);
+  y_forward_to_global(L, (half == 0 ? Pa : Pb) + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // ---- adjoint kernels ---------------------------------------------------------
@@ -1140,56 +1158,69 @@ __global__ __launch_bounds__(kThreadsZ) void k_zdiv_sum(const float2* __restrict
   z_inv0_store<NX, NY, NZ>(L.T[0], out, kx, p0, L.twz, tid);
 }
 
-// rho^_xi <- b^2 rho^_xi + c0^2 dt/rho0 q + c0^2 S^T y^n; then W_xi = R2C(b rho^_xi),
-// or on the last (final != 0) step W_xi = R2C(u^_xi) for the initial-condition transpose.
+// rho^_xi <- b^2 rho^_xi + (c0^2 dt/rho0 q + c0^2 S^T y^n), q = C2R of the summed
+// divergence Qs; then W_xi = R2C(b rho^_xi), or on the last (final != 0) step
+// W_xi = R2C(u^_xi) for the initial-condition transpose. Slab z = blockIdx.x / 2
+// is split over two blocks sharing the one C2R: half 0 does rho_x and rho_y
+// (one C2R, two R2C), half 1 rho_z (one C2R, one R2C).
 template <int NX, int NY, int NZ, typename V>
 __global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restrict__ Qs, WaveBuffers B,
                                                           const float* __restrict__ yplane, WaveTables t,
                                                           WaveScalars sc, int final_step) {
   using D = Dims<NX, NY, NZ>;
   __shared__ SlabLds<NX, NY, NZ, V> L;
-  const int tid = threadIdx.x;
-  int z, xi;
-  slab_field_of_block(blockIdx.x, z, xi);
+  const int z = blockIdx.x >> 1, half = blockIdx.x & 1, tid = threadIdx.x;
+  const int xi0 = half == 0 ? 0 : 2, nxi = half == 0 ? 2 : 1;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
-  const float2* ub = reinterpret_cast<const float2*>(B.u[xi]) + rz;
   float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
   y_load<NX, NY, NZ>(ry, Qs + cz, tid);
-  float2 ro[D::IX0][D::RX0], src[D::IX0][D::RX0];
-  load_real<NX, NY, NZ>(ro, rb, tid);
+  float2 src[D::IX0][D::RX0];
   if (z == 0) load_real<NX, NY, NZ>(src, reinterpret_cast<const float2*>(yplane), tid);   // data source
-  load_slab_tables(L, t, xi == 0 ? t.bx : nullptr, xi == 1 ? t.by : nullptr, (const V*)nullptr, 0, tid);
+  load_slab_tables(L, t, half == 0 ? t.bx : nullptr, half == 0 ? t.by : nullptr, (const V*)nullptr, 0, tid);
   const float bzz = t.bz[z];
   __syncthreads();
   y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
   float2 q[D::IX0][D::RX0];
   x_inverse_to_regs(L, q, tid);
   const float qs = sc.c2 * sc.dt_over_rho0;
-  const float ss = z == 0 ? sc.c2 : 0.f;
 #pragma unroll
-  for (int i = 0; i < D::IX0; ++i) {
-    const RowItem<NX, NY, NZ> it(tid, i);
-    if (it.ok) {
+  for (int i = 0; i < D::IX0; ++i)
 #pragma unroll
-      for (int m = 0; m < D::RX0; ++m) {
-        const int n = it.n(m);
-        float b0, b1;
-        if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
-        else if (xi == 1) { b0 = b1 = L.py[it.y]; }
-        else { b0 = b1 = bzz; }
-        const float2 sv = z == 0 ? src[i][m] : make_float2(0.f, 0.f);
-        const float2 rn = make_float2(b0 * b0 * ro[i][m].x + qs * q[i][m].x + ss * sv.x,
-                                      b1 * b1 * ro[i][m].y + qs * q[i][m].y + ss * sv.y);
-        rb[it.pair(m)] = rn;
-        q[i][m] = make_float2(b0 * rn.x, b1 * rn.y);
+    for (int m = 0; m < D::RX0; ++m) {
+      q[i][m] = make_float2(qs * q[i][m].x, qs * q[i][m].y);
+      if (z == 0) q[i][m] = make_float2(q[i][m].x + sc.c2 * src[i][m].x, q[i][m].y + sc.c2 * src[i][m].y);
+    }
+#pragma unroll 1
+  for (int c = 0; c < nxi; ++c) {
+    const int xi = xi0 + c;
+    int tl = tid;   // opaque copy: addresses are recomputed per component, not kept live
+    asm volatile("" : "+v"(tl));
+    float2* rb = reinterpret_cast<float2*>(B.rho[xi]) + rz;
+    float2 ro[D::IX0][D::RX0], w[D::IX0][D::RX0];
+    load_real<NX, NY, NZ>(ro, rb, tl);
+    if (c > 0) __syncthreads();   // the previous component's y pass is done with S
+#pragma unroll
+    for (int i = 0; i < D::IX0; ++i) {
+      const RowItem<NX, NY, NZ> it(tl, i);
+      if (it.ok) {
+#pragma unroll
+        for (int m = 0; m < D::RX0; ++m) {
+          const int n = it.n(m);
+          float b0, b1;
+          if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
+          else if (xi == 1) { b0 = b1 = L.py[it.y]; }
+          else { b0 = b1 = bzz; }
+          const float2 rn = make_float2(b0 * b0 * ro[i][m].x + q[i][m].x, b1 * b1 * ro[i][m].y + q[i][m].y);
+          rb[it.pair(m)] = rn;
+          w[i][m] = make_float2(b0 * rn.x, b1 * rn.y);
+        }
       }
     }
+    // last step: the initial-condition transpose needs R2C(u^) instead (read once per adjoint)
+    if (final_step) load_real<NX, NY, NZ>(w, reinterpret_cast<const float2*>(B.u[xi]) + rz, tl);
+    x_forward_from_regs(L, w, tl);
+    y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tl);
   }
-  // last step: the initial-condition transpose needs R2C(u^) instead (read once per adjoint)
-  if (final_step) load_real<NX, NY, NZ>(q, ub, tid);
-  x_forward_from_regs(L, q, tid);
-  y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // p = (rho^_x + rho^_y + rho^_z)/(3 c0^2) - dt/(2 rho0) sum_xi Dminus_xi u^_xi.
@@ -1253,10 +1284,11 @@ hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBu
   using D = Dims<NX, NY, NZ>;
   constexpr int NT = kThreadsSlab;
   const size_t npix = (size_t)NX * NY;
-  k_fwd_init<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(p0, B, planes, t, sc);
+  k_fwd_init<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(p0, B, planes, planes + (size_t)nt * npix, t, sc);
   for (int n = 0; n < nt - 1; ++n) {
     timed(kt, K_ZGRAD, st, [&] {
-      k_zgrad<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], t, sc.inv_ntot);
+      k_zgrad<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], n == 0 ? 1 : 2, B.spec[0],
+                                                             B.spec[1], t, sc.inv_ntot);
     });
     timed(kt, K_FWD_U, st, [&] {
       k_fwd_u<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], B.spec[1], B, t,
@@ -1267,8 +1299,9 @@ hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBu
                                                                              sc.inv_ntot);
     });
     timed(kt, K_FWD_RHO, st, [&] {
-      k_fwd_rho<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0],
-                                                   planes + (size_t)(n + 1) * npix, t, sc);
+      k_fwd_rho<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0], B.spec[1],
+                                                       planes + (size_t)(n + 1) * npix,
+                                                       planes + (size_t)(nt + n + 1) * npix, t, sc);
     });
   }
   return hipGetLastError();
@@ -1296,7 +1329,7 @@ hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBu
                                                                 sc.inv_ntot);
     });
     timed(kt, K_ADJ_RHO, st, [&] {
-      k_adj_rho<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B.spec[3], B, planes + (size_t)n * npix, t, sc,
+      k_adj_rho<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B.spec[3], B, planes + (size_t)n * npix, t, sc,
                                                       n == 0 ? 1 : 0);
     });
   }

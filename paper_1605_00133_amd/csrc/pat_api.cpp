@@ -39,7 +39,7 @@ constexpr int kRedSlots = 16;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u[3], rho[3], spec[4], planes2, planes, red_partial, red_out;
+  size_t u[3], rho[3], spec[4], planes2, planes, red_partial, red_out, flags;
   size_t img[7], dual, data[6];
   size_t total;
 };
@@ -67,6 +67,7 @@ Layout make_layout(const pat_grid& g, const pat_sampling& s) {
   L.planes = s.kind == PAT_SAMPLE_FULL ? 0 : take((size_t)g.nt * n_pix(g) * sizeof(float));
   L.red_partial = take(kRedBlocks * sizeof(double));
   L.red_out = take(kRedSlots * sizeof(double));
+  L.flags = take((size_t)g.nz * sizeof(unsigned));
   for (int i = 0; i < 7; ++i) L.img[i] = take(R);
   L.dual = take(n_dual(g, 1) * sizeof(float));
   const size_t D = (size_t)g.nt * s.mc * sizeof(float);
@@ -188,6 +189,7 @@ struct pat_plan {
   float* planes;
   double* red_partial;
   double* red_out;
+  HandOff handoff;          // slab-pair flags (workspace) and launch epoch
   float* img[7];
   float* dual;
   float* data[6];
@@ -337,7 +339,7 @@ pat_status op_forward(pat_plan* P, const float* p0, float* f) {
   float* planes = P->kind == PAT_SAMPLE_FULL ? f : P->planes;
   const long nplane = (long)P->g.nt * P->npix;
   PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, P->planes2, P->g.nt, P->stream,
-                               P->timer.ev ? &P->timer : nullptr));
+                                        P->timer.ev ? &P->timer : nullptr, P->handoff));
   PAT_TRY_HIP(launch_sum2(P->planes2, nplane, planes, nplane, P->stream));
   if (P->kind == PAT_SAMPLE_POINTS)
     PAT_TRY_HIP(launch_rsp_gather(planes, P->idx, f, P->npix, P->mc, P->g.nt, P->stream));
@@ -356,7 +358,7 @@ pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
     planes = P->planes;
   }
   PAT_TRY_HIP(P->impl->adjoint[P->fftp](P->tabs, P->sc, P->wb, planes, p, P->g.nt, P->stream,
-                               P->timer.ev ? &P->timer : nullptr));
+                                        P->timer.ev ? &P->timer : nullptr, P->handoff));
   return PAT_OK;
 }
 
@@ -476,6 +478,17 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
   P->planes = smp->kind == PAT_SAMPLE_FULL ? nullptr : ws_ptr<float>(P, L.planes);
   P->red_partial = ws_ptr<double>(P, L.red_partial);
   P->red_out = ws_ptr<double>(P, L.red_out);
+  P->handoff.flags = ws_ptr<unsigned>(P, L.flags);
+  P->handoff.epoch = 0;   // launches tag the flags with epochs 1, 2, ...
+  {
+    hipError_t e = hipMemsetAsync(P->handoff.flags, 0, (size_t)grid->nz * sizeof(unsigned), P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(P->tables);
+      delete P;
+      return set_error(PAT_ERR_HIP, "clearing the hand-off flags: %s", hipGetErrorString(e));
+    }
+  }
   for (int i = 0; i < 7; ++i) P->img[i] = ws_ptr<float>(P, L.img[i]);
   P->dual = ws_ptr<float>(P, L.dual);
   for (int i = 0; i < 6; ++i) P->data[i] = ws_ptr<float>(P, L.data[i]);

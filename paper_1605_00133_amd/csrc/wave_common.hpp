@@ -79,12 +79,19 @@ struct KernelTimer {
   int count;
 };
 
+// Hand-off flags of the slab-pair velocity passes (device, >= nz entries, zero
+// at plan creation) and the host-side launch epoch that tags them.
+struct HandOff {
+  unsigned* flags;
+  unsigned epoch;
+};
+
 // Forward: planes receives two sensor-plane series, [2][nt][ny][nx] (the two
 // halves of the density pass); their sum is p on the plane z = 0.
 using WaveLaunchFwd = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
-                                     const float* p0, float* planes2, int nt, hipStream_t, KernelTimer*);
+                                     const float* p0, float* planes2, int nt, hipStream_t, KernelTimer*, HandOff&);
 using WaveLaunchAdj = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&,
-                                     const float* planes, float* p, int nt, hipStream_t, KernelTimer*);
+                                     const float* planes, float* p, int nt, hipStream_t, KernelTimer*, HandOff&);
 
 // FFT arithmetic of the propagator kernels: FP32, or FP64 in registers and
 // LDS with FP32 storage in HBM.

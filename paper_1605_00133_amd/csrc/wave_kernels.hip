@@ -877,32 +877,99 @@ __global__ __launch_bounds__(kThreadsZ) void k_zmul(float2* H0, float2* H1, floa
   z_inv0_store<NX, NY, NZ>(L.T[0], H, kx, p0, L.twz, tid);
 }
 
-// Velocity update of component xi for slab z, then R2C of the new u_xi.
-// Q, Gz: outputs of k_zgrad; U0, U1, U2: spectra of the new u components
-// (U2 aliases Gz: only this block reads Gz[z] and it does so before writing).
-template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict__ Q, const float2* Gz,
-                                                        float2* U0, float2* U1, float2* U2, WaveBuffers B,
-                                                        WaveTables t, WaveScalars sc, int init) {
+// ---- slab pairs -----------------------------------------------------------------
+// The velocity passes have three components per slab, six 2D transforms. With
+// one workgroup per CU (the FP64 slab fills the LDS), 3 nz workgroups of two
+// transforms would take two rounds on 256 CUs; instead 2 nz workgroups take
+// three transforms each: half 0 of slab z does the C2R and update of the z
+// component and the whole x component, half 1 the whole y component and then
+// the R2C of the z component, from the field half 0 handed over through
+// global memory (flag per slab, tagged with the launch's epoch). The two
+// halves of a slab are block ids 8 apart (same XCD). All 2 nz <= 256
+// workgroups of a launch are resident at once, so the wait ends; it is bounded
+// anyway, and on a time-out the half writes NaN (caught downstream) instead of
+// hanging. The pairing is independent of which XCDs the halves land on.
+constexpr int kHandoffSpin = 1 << 18;   // x ~128 cycles: ~14 ms
+
+__device__ __forceinline__ void slab_pair_of_block(int b, int& z, int& half) {
+  z = (b >> 4) * 8 + (b & 7);
+  half = (b >> 3) & 1;
+}
+
+// The handed-over slab is written and read with system-coherent accesses
+// (write-through to the point of coherence, no cache on the way back), so the
+// hand-off needs no cache write-back or invalidation: the producer waits for its
+// stores to complete, then raises the flag; the consumer polls the flag and
+// reads the slab the same way.
+__device__ __forceinline__ void st_coherent(float2* p, float2 v) {
+  unsigned long long x;
+  __builtin_memcpy(&x, &v, sizeof(x));
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ float2 ld_coherent(const float2* p) {
+  const unsigned long long x =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  float2 v;
+  __builtin_memcpy(&v, &x, sizeof(v));
+  return v;
+}
+
+__device__ __forceinline__ void handoff_publish(unsigned* flag, unsigned epoch) {
+  __builtin_amdgcn_s_waitcnt(0);   // this thread's coherent stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Returns false on a time-out. Ends with a workgroup barrier.
+__device__ __forceinline__ bool handoff_wait(const unsigned* flag, unsigned epoch) {
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    int it = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != epoch && ++it < kHandoffSpin)
+      __builtin_amdgcn_s_sleep(2);
+    s_ok = it < kHandoffSpin;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Coherent read of a real slab in the register layout (the consumer side).
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void load_real_coherent(RealRegs<NX, NY, NZ>& r, const float2* src, int tid) {
   using D = Dims<NX, NY, NZ>;
-  __shared__ SlabLds<NX, NY, NZ, V> L;
+#pragma unroll
+  for (int i = 0; i < D::IX0; ++i) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    if (it.ok) {
+#pragma unroll
+      for (int m = 0; m < D::RX0; ++m) r[i][m] = ld_coherent(src + it.pair(m));
+    }
+  }
+}
+
+// C2R of component xi's spectrum slab, the velocity update, and the R2C input
+// in w (register layout). ADJ = false (forward): src = Q (x, y: times the kx or
+// ky_pos derivative factor) or Gz; u <- a (a u - dt/rho0 g), w = new u.
+// ADJ = true: src = W_xi; uh = u^ + dt rho0 g, u^ <- a^2 uh, w = a uh.
+// Starts with the table loads (caller makes sure LDS is free); no barrier at the end.
+template <int NX, int NY, int NZ, typename V, bool ADJ, bool COH = false>
+__device__ __forceinline__ void u_c2r_update(SlabLds<NX, NY, NZ, V>& L, const float2* src, int xi, int z,
+                                             const WaveBuffers& B, const WaveTables& t, const WaveScalars& sc,
+                                             int init, RealRegs<NX, NY, NZ>& w, int tid) {
+  using D = Dims<NX, NY, NZ>;
   const auto& tab = TabSel<V>::get(t);
-  const int tid = threadIdx.x;
-  int z, xi;
-  slab_field_of_block(blockIdx.x, z, xi);
-  const size_t cz = (size_t)z * D::SLAB_C;
+  const int mode = ADJ || xi == 2 ? 0 : xi + 1;
   float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
   float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
-  y_load<NX, NY, NZ>(ry, (xi == 2 ? Gz : Q) + cz, tid);
+  y_load<NX, NY, NZ>(ry, src + (size_t)z * D::SLAB_C, tid);
   float2 uo[D::IX0][D::RX0];
-  if (!init) load_real<NX, NY, NZ>(uo, u, tid);   // in flight during the transform
+  if (ADJ || !init) load_real<NX, NY, NZ>(uo, u, tid);   // in flight during the transform
   load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr,
-                   xi == 0 ? tab.mpx : (xi == 1 ? tab.mpy : (const V*)nullptr), xi == 2 ? 0 : xi + 1, tid);
+                   mode == 1 ? tab.mpx : (mode == 2 ? tab.mpy : (const V*)nullptr), mode, tid);
   const float azz = t.az[z];
   __syncthreads();
-  y_inverse(L, ry, xi == 2 ? 0 : xi + 1, TabSel<V>::get(t).tw_y, tid);
-  float2 g[D::IX0][D::RX0];
-  x_inverse_to_regs(L, g, tid);
+  y_inverse(L, ry, mode, tab.tw_y, tid);
+  x_inverse_to_regs(L, w, tid);
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
     const RowItem<NX, NY, NZ> it(tid, i);
@@ -914,18 +981,58 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
         if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
         else if (xi == 1) { a0 = a1 = L.py[it.y]; }
         else { a0 = a1 = azz; }
-        const float2 gv = g[i][m];
-        const float2 o = init ? make_float2(gv.x * sc.half_dt_over_rho0, gv.y * sc.half_dt_over_rho0) : uo[i][m];
-        const float2 un = make_float2(a0 * (a0 * o.x - sc.dt_over_rho0 * gv.x),
-                                      a1 * (a1 * o.y - sc.dt_over_rho0 * gv.y));
-        u[it.pair(m)] = un;
-        g[i][m] = un;
+        const float2 g = w[i][m];
+        if (!ADJ) {
+          const float2 o = init ? make_float2(g.x * sc.half_dt_over_rho0, g.y * sc.half_dt_over_rho0) : uo[i][m];
+          const float2 un = make_float2(a0 * (a0 * o.x - sc.dt_over_rho0 * g.x), a1 * (a1 * o.y - sc.dt_over_rho0 * g.y));
+          if (COH) st_coherent(u + it.pair(m), un);   // handed over to the partner block
+          else u[it.pair(m)] = un;
+          w[i][m] = un;
+        } else {
+          const float2 uh = make_float2(uo[i][m].x + sc.dt_rho0 * g.x, uo[i][m].y + sc.dt_rho0 * g.y);
+          u[it.pair(m)] = make_float2(a0 * a0 * uh.x, a1 * a1 * uh.y);
+          w[i][m] = make_float2(a0 * uh.x, a1 * uh.y);
+        }
       }
     }
   }
-  x_forward_from_regs(L, g, tid);
-  float2* U = xi == 0 ? U0 : (xi == 1 ? U1 : U2);
-  y_forward_to_global(L, U + cz, TabSel<V>::get(t).tw_y, tid);
+}
+
+// Velocity pass of the forward step (see "slab pairs"): U_x, U_y and, in place
+// of Gz, U_z = R2C of the new velocity components.
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict__ Q, float2* Gz, float2* Ux,
+                                                        float2* Uy, WaveBuffers B, WaveTables t, WaveScalars sc,
+                                                        int init, unsigned* flags, unsigned epoch) {
+  using D = Dims<NX, NY, NZ>;
+  __shared__ SlabLds<NX, NY, NZ, V> L;
+  const auto& twy = TabSel<V>::get(t).tw_y;
+  const int tid = threadIdx.x;
+  int z, half;
+  slab_pair_of_block(blockIdx.x, z, half);
+  const size_t cz = (size_t)z * D::SLAB_C;
+  float2 w[D::IX0][D::RX0];
+  if (half == 0) {
+    u_c2r_update<NX, NY, NZ, V, false, true>(L, Gz, 2, z, B, t, sc, init, w, tid);
+    handoff_publish(flags + z, epoch);
+    u_c2r_update<NX, NY, NZ, V, false>(L, Q, 0, z, B, t, sc, init, w, tid);
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, Ux + cz, twy, tid);
+  } else {
+    u_c2r_update<NX, NY, NZ, V, false>(L, Q, 1, z, B, t, sc, init, w, tid);
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, Uy + cz, twy, tid);
+    const bool ok = handoff_wait(flags + z, epoch);
+    load_real_coherent<NX, NY, NZ>(w, reinterpret_cast<const float2*>(B.u[2]) + (size_t)z * D::SLAB_P, tid);
+    if (!ok) {
+#pragma unroll
+      for (int i = 0; i < D::IX0; ++i)
+#pragma unroll
+        for (int m = 0; m < D::RX0; ++m) w[i][m] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    }
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, Gz + cz, twy, tid);
+  }
 }
 
 // Density update of slab z = blockIdx.x / 2. The slab's work is split over two
@@ -1052,45 +1159,51 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_init(const float* __restri
 }
 
 // u^_xi: uh = u^ + dt rho0 Dplus_xi(b rho^) (the pencil pass already applied the
-// multiplier), u^ <- a^2 uh, W_xi = R2C(a uh) in place.
+// multiplier), u^ <- a^2 uh, W_xi = R2C(a uh) in place, as slab pairs (see
+// "slab pairs"; the z component's a uh is handed over in its own spectrum slab,
+// which is free once half 0 has read it).
 template <int NX, int NY, int NZ, typename V>
-__global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc) {
+__global__ __launch_bounds__(kThreadsSlab) void k_adj_u(WaveBuffers B, WaveTables t, WaveScalars sc,
+                                                        unsigned* flags, unsigned epoch) {
   using D = Dims<NX, NY, NZ>;
   __shared__ SlabLds<NX, NY, NZ, V> L;
+  const auto& twy = TabSel<V>::get(t).tw_y;
   const int tid = threadIdx.x;
-  int z, xi;
-  slab_field_of_block(blockIdx.x, z, xi);
+  int z, half;
+  slab_pair_of_block(blockIdx.x, z, half);
   const size_t cz = (size_t)z * D::SLAB_C;
-  float2* ub = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
-  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
-  y_load<NX, NY, NZ>(ry, B.spec[xi] + cz, tid);
-  float2 uo[D::IX0][D::RX0];
-  load_real<NX, NY, NZ>(uo, ub, tid);
-  load_slab_tables(L, t, xi == 0 ? t.ax : nullptr, xi == 1 ? t.ay : nullptr, (const V*)nullptr, 0, tid);
-  const float azz = t.az[z];
-  __syncthreads();
-  y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
-  float2 g[D::IX0][D::RX0];
-  x_inverse_to_regs(L, g, tid);
+  float2* hand = reinterpret_cast<float2*>(B.spec[2] + cz);   // SLAB_P float2 fit in a SLAB_C slab
+  float2 w[D::IX0][D::RX0];
+  if (half == 0) {
+    u_c2r_update<NX, NY, NZ, V, true>(L, B.spec[2], 2, z, B, t, sc, 0, w, tid);
 #pragma unroll
-  for (int i = 0; i < D::IX0; ++i) {
-    const RowItem<NX, NY, NZ> it(tid, i);
-    if (it.ok) {
+    for (int i = 0; i < D::IX0; ++i) {
+      const RowItem<NX, NY, NZ> it(tid, i);
+      if (it.ok) {
 #pragma unroll
-      for (int m = 0; m < D::RX0; ++m) {
-        const int n = it.n(m);
-        float a0, a1;
-        if (xi == 0) { a0 = L.px[2 * n]; a1 = L.px[2 * n + 1]; }
-        else if (xi == 1) { a0 = a1 = L.py[it.y]; }
-        else { a0 = a1 = azz; }
-        const float2 uh = make_float2(uo[i][m].x + sc.dt_rho0 * g[i][m].x, uo[i][m].y + sc.dt_rho0 * g[i][m].y);
-        ub[it.pair(m)] = make_float2(a0 * a0 * uh.x, a1 * a1 * uh.y);
-        g[i][m] = make_float2(a0 * uh.x, a1 * uh.y);
+        for (int m = 0; m < D::RX0; ++m) st_coherent(hand + it.pair(m), w[i][m]);
       }
     }
+    handoff_publish(flags + z, epoch);
+    u_c2r_update<NX, NY, NZ, V, true>(L, B.spec[0], 0, z, B, t, sc, 0, w, tid);
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, B.spec[0] + cz, twy, tid);
+  } else {
+    u_c2r_update<NX, NY, NZ, V, true>(L, B.spec[1], 1, z, B, t, sc, 0, w, tid);
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, B.spec[1] + cz, twy, tid);
+    const bool ok = handoff_wait(flags + z, epoch);
+    load_real_coherent<NX, NY, NZ>(w, hand, tid);
+    if (!ok) {
+#pragma unroll
+      for (int i = 0; i < D::IX0; ++i)
+#pragma unroll
+        for (int m = 0; m < D::RX0; ++m) w[i][m] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    }
+    __syncthreads();   // every lane has its a uh before the slab is overwritten
+    x_forward_from_regs(L, w, tid);
+    y_forward_to_global(L, B.spec[2] + cz, twy, tid);
   }
-  x_forward_from_regs(L, g, tid);
-  y_forward_to_global(L, B.spec[xi] + cz, TabSel<V>::get(t).tw_y, tid);
 }
 
 // Pencil pass of the summed divergence: out = IFFT_z[ sum_xi kappa/N i k_xi
@@ -1266,6 +1379,11 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __rest
 
 // ---- launch sequences ----------------------------------------------------------
 
+inline unsigned next_epoch(HandOff& ho) {   // never 0, the value of a cleared flag
+  if (++ho.epoch == 0) ho.epoch = 1;
+  return ho.epoch;
+}
+
 template <typename F>
 inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
   const bool on = kt && (kt->which == id || kt->which == -2) && kt->count < kt->cap;
@@ -1280,7 +1398,7 @@ inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
 
 template <int NX, int NY, int NZ, typename V>
 hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
-                        const float* p0, float* planes, int nt, hipStream_t st, KernelTimer* kt) {
+                        const float* p0, float* planes, int nt, hipStream_t st, KernelTimer* kt, HandOff& ho) {
   using D = Dims<NX, NY, NZ>;
   constexpr int NT = kThreadsSlab;
   const size_t npix = (size_t)NX * NY;
@@ -1291,8 +1409,8 @@ hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBu
                                                              B.spec[1], t, sc.inv_ntot);
     });
     timed(kt, K_FWD_U, st, [&] {
-      k_fwd_u<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], B.spec[1], B, t,
-                                                     sc, n == 0 ? 1 : 0);
+      k_fwd_u<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], B, t, sc,
+                                                     n == 0 ? 1 : 0, ho.flags, next_epoch(ho));
     });
     timed(kt, K_ZDIV, st, [&] {
       k_zmul<NX, NY, NZ, V, false><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], t,
@@ -1309,7 +1427,7 @@ hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBu
 
 template <int NX, int NY, int NZ, typename V>
 hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B,
-                        const float* planes, float* p, int nt, hipStream_t st, KernelTimer* kt) {
+                        const float* planes, float* p, int nt, hipStream_t st, KernelTimer* kt, HandOff& ho) {
   using D = Dims<NX, NY, NZ>;
   constexpr int NT = kThreadsSlab;
   const size_t npix = (size_t)NX * NY;
@@ -1323,7 +1441,9 @@ hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBu
       k_zmul<NX, NY, NZ, V, true><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], t,
                                                                             sc.inv_ntot);
     });
-    timed(kt, K_ADJ_U, st, [&] { k_adj_u<NX, NY, NZ, V><<<3 * NZ, NT, 0, st>>>(B, t, sc); });
+    timed(kt, K_ADJ_U, st, [&] {
+      k_adj_u<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B, t, sc, ho.flags, next_epoch(ho));
+    });
     timed(kt, K_ZDIV_SUM, st, [&] {
       k_zdiv_sum<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], t,
                                                                 sc.inv_ntot);

@@ -19,6 +19,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -36,11 +37,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def code_only(text):
+    """Source text without comments and blank lines (comment edits keep the hash)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).strip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
+def kernel_source_hash(read=None):
+    """Hash of the propagator kernel sources (code only)."""
     h = hashlib.sha256()
     for f in ("wave_kernels.hip", "fft_radix.hpp", "wave_common.hpp"):
-        with open(os.path.join(ROOT, "paper_1605_00133_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join(ROOT, "paper_1605_00133_amd", "csrc", f)
+        text = read(f) if read else open(path, encoding="utf-8").read()
+        h.update(code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -886,9 +886,11 @@ __global__ __launch_bounds__(kThreadsZ) void k_zmul(float2* H0, float2* H1, floa
 // the R2C of the z component, from the field half 0 handed over through
 // global memory (flag per slab, tagged with the launch's epoch). The two
 // halves of a slab are block ids 8 apart (same XCD). All 2 nz <= 256
-// workgroups of a launch are resident at once, so the wait ends; it is bounded
-// anyway, and on a time-out the half writes NaN (caught downstream) instead of
-// hanging. The pairing is independent of which XCDs the halves land on.
+// workgroups of a launch fit on the chip at once; and should fewer fit (other
+// work holding CUs), the producer of a slab has the lower block id, so it was
+// dispatched before its consumer and, never waiting itself, finishes: the wait
+// ends either way. It is bounded anyway, and on a time-out the half writes NaN
+// (caught downstream) instead of hanging.
 constexpr int kHandoffSpin = 1 << 18;   // x ~128 cycles: ~14 ms
 
 __device__ __forceinline__ void slab_pair_of_block(int b, int& z, int& half) {

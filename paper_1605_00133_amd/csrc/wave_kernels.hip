@@ -212,54 +212,53 @@ __device__ __forceinline__ void load_real(RealRegs<NX, NY, NZ>& r, const float2*
 
 // ---- slab transforms -------------------------------------------------------
 
-// Work items of the y stages. Columns kx < MX are the main items, laid out so
-// that a wave of 64 lanes holds 64 consecutive columns of one butterfly (for
-// MX a multiple of 64 the butterfly index, and hence its twiddles, is
-// wave-uniform); the Nyquist column kx = MX is an extra item for the first threads.
-//   stage 1 (M-point blocks mb < R0): main item b -> kx = b % MX, mb = b / MX
-//   stage 0 (R0-point butterflies n1 < M): main item b -> kx = b % MX, n1 = b / MX
+// Work items of the y stages. After the x transform the columns kx = 0 and
+// kx = MX of a slab both hold transforms of real sequences along y (X[0] and
+// X[MX] of a real row are real), so the slab keeps them packed as one complex
+// column X[0] + i X[MX] at kx = 0 and the y stages run over MX columns only;
+// the pair is split again where the column meets the spectrum in HBM. A wave
+// of 64 lanes holds 64 consecutive columns of one butterfly (for MX a multiple
+// of 64 the butterfly index, and hence its twiddles, is wave-uniform).
+//   stage 1: item b -> kx = b % MX and the pair of M-point blocks c = b / MX and
+//            mate(c) (frequencies f and -f lie in blocks c and R0 - c, blocks 0
+//            and R0/2 hold their own negatives), so the thread that owns the
+//            packed column's pair can split it in registers
+//   stage 0 (R0-point butterflies n1 < M): item b -> kx = b % MX, n1 = b / MX
 template <int NX, int NY, int NZ>
 struct YItems {
   using D = Dims<NX, NY, NZ>;
-  static constexpr int N1 = D::MX * D::RY0, I1 = cdiv(N1, kThreadsSlab);   // stage 1 main
-  static constexpr int N0 = D::MX * D::MYB, I0 = cdiv(N0, kThreadsSlab);   // stage 0 main
+  static constexpr int CY = D::RY0 / 2;                                     // block pairs
+  static constexpr int N1 = D::MX * CY, I1 = cdiv(N1, kThreadsSlab);        // stage 1
+  static constexpr int N0 = D::MX * D::MYB, I0 = cdiv(N0, kThreadsSlab);    // stage 0
   static constexpr bool UNIFORM = D::MX % 64 == 0;
-  static __device__ __forceinline__ bool s1(int tid, int i, int& kx, int& mb) {
-    if (i < I1) {
-      const int b = tid + i * kThreadsSlab;
-      kx = b % D::MX;
-      mb = b / D::MX;
-      return b < N1;
-    }
-    kx = D::MX;
-    mb = tid;
-    return tid < D::RY0;
+  static_assert(D::RY0 >= 4 && D::RY0 % 2 == 0, "y block pairs need an even first radix");
+  static __device__ __forceinline__ int mate(int c) { return c == 0 ? D::RY0 / 2 : D::RY0 - c; }
+  static __device__ __forceinline__ bool s1(int tid, int i, int& kx, int& c) {
+    const int b = tid + i * kThreadsSlab;
+    kx = b % D::MX;
+    c = b / D::MX;
+    return b < N1;
   }
   static __device__ __forceinline__ bool s0(int tid, int i, int& kx, int& n1) {
-    if (i < I0) {
-      const int b = tid + i * kThreadsSlab;
-      kx = b % D::MX;
-      n1 = b / D::MX;
-      return b < N0;
-    }
-    kx = D::MX;
-    n1 = tid;
-    return tid < D::MYB;
+    const int b = tid + i * kThreadsSlab;
+    kx = b % D::MX;
+    n1 = b / D::MX;
+    return b < N0;
   }
 };
 
 template <typename V> using ConstTab = __attribute__((address_space(4))) const V;
 
-// y stage-0 twiddles of butterfly n1: for main items with a wave-uniform n1 they
-// come through the scalar cache from the natural table tw_y (global, read-only);
-// otherwise from the transposed LDS table.
+// y stage-0 twiddles of butterfly n1: with a wave-uniform n1 they come through
+// the scalar cache from the natural table tw_y (global, read-only); otherwise
+// from the transposed LDS table.
 template <int NX, int NY, int NZ, bool INV, typename V>
 __device__ __forceinline__ void y_twiddle(V* a, const SlabLds<NX, NY, NZ, V>& L, const V* __restrict__ twg,
-                                          int n1, bool main_item) {
+                                          int n1) {
   using D = Dims<NX, NY, NZ>;
   constexpr int M = D::MYB, R0 = D::RY0;
   if constexpr (M > 1) {
-    if (YItems<NX, NY, NZ>::UNIFORM && main_item) {
+    if constexpr (YItems<NX, NY, NZ>::UNIFORM) {
       using Sc = typename ScalarOf<V>::T;
       const int n1u = __builtin_amdgcn_readfirstlane(n1);
       ConstTab<Sc>* t = (ConstTab<Sc>*)twg;   // (re, im) pairs
@@ -274,31 +273,58 @@ __device__ __forceinline__ void y_twiddle(V* a, const SlabLds<NX, NY, NZ, V>& L,
   }
 }
 
-// Registers of the y stage-1 global loads (slot i, value k1).
-template <int NX, int NY, int NZ>
-using YRegs = float2[YItems<NX, NY, NZ>::I1 + 1][Dims<NX, NY, NZ>::MYB];
+// n consecutive complex values from g (16-byte aligned for even offsets) as
+// 16-byte loads where n is even.
+template <int n>
+__device__ __forceinline__ void load_run(float2 (&r)[n], const float2* __restrict__ g) {
+  if constexpr (n % 2 == 0) {
+#pragma unroll
+    for (int k = 0; k < n; k += 2) {
+      const float4 u = reinterpret_cast<const float4*>(g)[k / 2];
+      r[k] = make_float2(u.x, u.y);
+      r[k + 1] = make_float2(u.z, u.w);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < n; ++k) r[k] = g[k];
+  }
+}
 
-// Global loads of the slab spectrum g[kx][ky_pos] in the stage-1 butterfly
-// layout; issued before anything else a kernel waits on, so their latency
-// overlaps the table loads and the barrier that follows.
+// Registers of the y stage-1 global loads: the two blocks (c, mate(c)) of the
+// item's column, and for kx = 0 the same blocks of column MX.
+template <int NX, int NY, int NZ>
+struct YRegs {
+  float2 v[YItems<NX, NY, NZ>::I1][2][Dims<NX, NY, NZ>::MYB];
+  float2 n[YItems<NX, NY, NZ>::I1][2][Dims<NX, NY, NZ>::MYB];
+};
+
+// Global loads of the slab spectrum g[kx][ky_pos] in the stage-1 layout; issued
+// before anything else a kernel waits on, so their latency overlaps the table
+// loads and the barrier that follows.
 template <int NX, int NY, int NZ>
 __device__ __forceinline__ void y_load(YRegs<NX, NY, NZ>& r, const float2* __restrict__ g, int tid) {
   using D = Dims<NX, NY, NZ>;
   using Y = YItems<NX, NY, NZ>;
   constexpr int M = D::MYB;
 #pragma unroll
-  for (int i = 0; i <= Y::I1; ++i) {
-    int kx, mb;
-    if (Y::s1(tid, i, kx, mb)) {
-#pragma unroll
-      for (int k1 = 0; k1 < M; ++k1) r[i][k1] = g[kx * NY + M * mb + k1];
+  for (int i = 0; i < Y::I1; ++i) {
+    int kx, c;
+    if (Y::s1(tid, i, kx, c)) {
+      const int mc = Y::mate(c);
+      load_run<M>(r.v[i][0], g + kx * NY + M * c);
+      load_run<M>(r.v[i][1], g + kx * NY + M * mc);
+      if (kx == 0) {
+        load_run<M>(r.n[i][0], g + D::MX * NY + M * c);
+        load_run<M>(r.n[i][1], g + D::MX * NY + M * mc);
+      }
     }
   }
 }
 
 // y inverse transform of the loaded slab spectrum (times an optional derivative
 // factor L.mul by kx (mode 1) or ky_pos (mode 2)); leaves the rows in natural
-// y order (index kx). Caller syncs before (tables); ends synced.
+// y order (index kx, column 0 = X[0] + i X[MX]). Caller syncs before (tables);
+// ends synced.
 template <int NX, int NY, int NZ, typename V>
 __device__ __forceinline__ void y_inverse(SlabLds<NX, NY, NZ, V>& L, const YRegs<NX, NY, NZ>& r, int mode,
                                           const V* __restrict__ twg, int tid) {
@@ -306,30 +332,45 @@ __device__ __forceinline__ void y_inverse(SlabLds<NX, NY, NZ, V>& L, const YRegs
   using Y = YItems<NX, NY, NZ>;
   constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
 #pragma unroll
-  for (int i = 0; i <= Y::I1; ++i) {
-    int kx, mb;
-    if (Y::s1(tid, i, kx, mb)) {
-      V a[M];
+  for (int i = 0; i < Y::I1; ++i) {
+    int kx, c;
+    if (Y::s1(tid, i, kx, c)) {
 #pragma unroll
-      for (int k1 = 0; k1 < M; ++k1) {
-        a[k1] = widen<V>(r[i][k1]);
-        if (mode == 1) a[k1] = cmul(a[k1], L.mul[kx]);
-        else if (mode == 2) a[k1] = cmul(a[k1], L.mul[M * mb + k1]);
+      for (int h = 0; h < 2; ++h) {
+        const int mb = h == 0 ? c : Y::mate(c);
+        V a[M];
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          a[k1] = widen<V>(r.v[i][h][k1]);
+          if (mode == 1) a[k1] = cmul(a[k1], L.mul[kx]);
+        }
+        if (kx == 0) {   // pack column MX in as the imaginary part
+#pragma unroll
+          for (int k1 = 0; k1 < M; ++k1) {
+            V u = widen<V>(r.n[i][h][k1]);
+            if (mode == 1) u = cmul(u, L.mul[D::MX]);
+            a[k1] = mkc<V>(a[k1].x - u.y, a[k1].y + u.x);
+          }
+        }
+        if (mode == 2) {
+#pragma unroll
+          for (int k1 = 0; k1 < M; ++k1) a[k1] = cmul(a[k1], L.mul[M * mb + k1]);
+        }
+        dft_r<M, true>(a);
+#pragma unroll
+        for (int n1 = 0; n1 < M; ++n1) L.S[sidx(M * mb + n1, kx, P)] = a[n1];
       }
-      dft_r<M, true>(a);
-#pragma unroll
-      for (int n1 = 0; n1 < M; ++n1) L.S[sidx(M * mb + n1, kx, P)] = a[n1];
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i <= Y::I0; ++i) {
+  for (int i = 0; i < Y::I0; ++i) {
     int kx, n1;
     if (Y::s0(tid, i, kx, n1)) {
       V a[R0];
 #pragma unroll
       for (int m = 0; m < R0; ++m) a[m] = L.S[sidx(n1 + M * m, kx, P)];
-      y_twiddle<NX, NY, NZ, true>(a, L, twg, n1, i < Y::I0);
+      y_twiddle<NX, NY, NZ, true>(a, L, twg, n1);
       dft_r<R0, true>(a);
 #pragma unroll
       for (int m = 0; m < R0; ++m) L.S[sidx(n1 + M * m, kx, P)] = a[m];
@@ -338,9 +379,31 @@ __device__ __forceinline__ void y_inverse(SlabLds<NX, NY, NZ, V>& L, const YRegs
   __syncthreads();
 }
 
-// y forward transform of the rows (natural y, index kx) into the slab spectrum
-// g[kx][ky_pos]: stage 0 in LDS, stage 1 straight from registers to HBM.
-// Caller syncs before.
+// The float2 view of LDS slab slot (row, idx): the spectrum, narrowed to its
+// storage precision, is staged in the slots it was computed in.
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ float2* slot_f2(SlabLds<NX, NY, NZ, V>& L, int row, int idx) {
+  return reinterpret_cast<float2*>(&L.S[sidx(row, idx, Dims<NX, NY, NZ>::PITCH)]);
+}
+
+// Split of the packed column's spectrum Z = Y0 + i YN (Y0, YN Hermitian) at
+// ky_pos p from Z[f] and Z[-f]: Y0 = (Z[f] + conj Z[-f]) / 2,
+// YN = (Z[f] - conj Z[-f]) / (2i); staged in slots (p, 0) and (p, MX).
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void y_split_stage(SlabLds<NX, NY, NZ, V>& L, int p, V zf, V zm) {
+  using Sc = typename ScalarOf<V>::T;
+  *slot_f2(L, p, 0) = narrow(mkc<V>((Sc)0.5 * (zf.x + zm.x), (Sc)0.5 * (zf.y - zm.y)));
+  *slot_f2(L, p, Dims<NX, NY, NZ>::MX) = narrow(mkc<V>((Sc)0.5 * (zf.y + zm.y), (Sc)0.5 * (zm.x - zf.x)));
+}
+
+// y forward transform of the rows (natural y, index kx, column 0 packed) into
+// the slab spectrum g[kx][ky_pos]. Stage 0 runs in LDS; stage 1 leaves its
+// outputs (float2) in the slots it read, every slot being read by exactly one
+// thread, so no barrier is needed before those writes; after a barrier the
+// slab is stored column by column, consecutive lanes on consecutive ky_pos
+// (512 contiguous bytes per wave instruction instead of one 64-byte run per
+// lane 1 KB apart, which the memory pipeline handles several times slower).
+// Caller syncs before; the caller syncs again before S is written.
 template <int NX, int NY, int NZ, typename V>
 __device__ __forceinline__ void y_forward_to_global(SlabLds<NX, NY, NZ, V>& L, float2* __restrict__ g,
                                                     const V* __restrict__ twg, int tid) {
@@ -348,30 +411,59 @@ __device__ __forceinline__ void y_forward_to_global(SlabLds<NX, NY, NZ, V>& L, f
   using Y = YItems<NX, NY, NZ>;
   constexpr int M = D::MYB, R0 = D::RY0, P = D::PITCH;
 #pragma unroll
-  for (int i = 0; i <= Y::I0; ++i) {
+  for (int i = 0; i < Y::I0; ++i) {
     int kx, n1;
     if (Y::s0(tid, i, kx, n1)) {
       V a[R0];
 #pragma unroll
       for (int m = 0; m < R0; ++m) a[m] = L.S[sidx(n1 + M * m, kx, P)];
       dft_r<R0, false>(a);
-      y_twiddle<NX, NY, NZ, false>(a, L, twg, n1, i < Y::I0);
+      y_twiddle<NX, NY, NZ, false>(a, L, twg, n1);
 #pragma unroll
       for (int k = 0; k < R0; ++k) L.S[sidx(n1 + M * k, kx, P)] = a[k];
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i <= Y::I1; ++i) {
-    int kx, mb;
-    if (Y::s1(tid, i, kx, mb)) {
-      V a[M];
+  for (int i = 0; i < Y::I1; ++i) {
+    int kx, c;
+    if (Y::s1(tid, i, kx, c)) {
+      const int mc = Y::mate(c);
+      V za[M], zb[M];
 #pragma unroll
-      for (int k1 = 0; k1 < M; ++k1) a[k1] = L.S[sidx(M * mb + k1, kx, P)];
-      dft_r<M, false>(a);
+      for (int k1 = 0; k1 < M; ++k1) {
+        za[k1] = L.S[sidx(M * c + k1, kx, P)];
+        zb[k1] = L.S[sidx(M * mc + k1, kx, P)];
+      }
+      dft_r<M, false>(za);
+      dft_r<M, false>(zb);
+      if (kx != 0) {
 #pragma unroll
-      for (int k1 = 0; k1 < M; ++k1) g[kx * NY + M * mb + k1] = narrow(a[k1]);
+        for (int k1 = 0; k1 < M; ++k1) {
+          *slot_f2(L, M * c + k1, kx) = narrow(za[k1]);
+          *slot_f2(L, M * mc + k1, kx) = narrow(zb[k1]);
+        }
+      } else if (c == 0) {   // blocks 0 and R0/2: -f in the same block
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          y_split_stage(L, k1, za[k1], za[(M - k1) % M]);
+          y_split_stage(L, M * mc + k1, zb[k1], zb[M - 1 - k1]);
+        }
+      } else {               // f in block c, -f in block R0 - c
+#pragma unroll
+        for (int k1 = 0; k1 < M; ++k1) {
+          y_split_stage(L, M * c + k1, za[k1], zb[M - 1 - k1]);
+          y_split_stage(L, M * mc + k1, zb[k1], za[M - 1 - k1]);
+        }
+      }
     }
+  }
+  __syncthreads();
+  // element e = kx * NY + ky_pos of the slab spectrum, kx = 0..MX
+#pragma unroll
+  for (int i = 0; i < cdiv(D::SLAB_C, kThreadsSlab); ++i) {
+    const int e = tid + i * kThreadsSlab;
+    if (e < D::SLAB_C) g[e] = *slot_f2(L, e % NY, e / NY);
   }
 }
 
@@ -419,13 +511,14 @@ struct PairItem {
   }
 };
 
-// Rows (natural kx, X[0..MX]) -> inverse x transform -> packed real pairs in
-// the register layout (unnormalised). Caller syncs before. Every exchange
-// stays inside the rows of one wave.
-template <int NX, int NY, int NZ, typename V>
-__device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, RealRegs<NX, NY, NZ>& out, int tid) {
+// Rows (natural kx, X[0..MX-1], slot 0 holding X[0] + i X[MX]) -> inverse x
+// transform -> packed real pairs (unnormalised), handed to out(i, m, value) in
+// the register layout (slot i, value m) as they come out. Caller syncs before.
+// Every exchange stays inside the rows of one wave.
+template <int NX, int NY, int NZ, typename V, typename F>
+__device__ __forceinline__ void x_inverse_apply(SlabLds<NX, NY, NZ, V>& L, int tid, F&& out) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX, P = D::PITCH;
+  constexpr int R0 = D::RX0, M = D::MXB, P = D::PITCH;
   V za[D::IXP][M], zb[D::IXP][M];
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
@@ -437,7 +530,6 @@ __device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, Rea
         xa[k1] = L.S[sidx(it.y, it.ma + R0 * k1, P)];
         xb[k1] = L.S[sidx(it.y, it.mb + R0 * k1, P)];
       }
-      const V xm = L.S[sidx(it.y, MX, P)];
       const V* wa = L.twn + it.ma;   // w^k for k = ma + R0 k1 at wa[R0 k1]
       const V* wb = L.twn + it.mb;
       // Partners are taken two at a time so each input dies as its outputs are
@@ -449,11 +541,13 @@ __device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, Rea
           za[i][k1] = split_inv(a, b, wa[R0 * k1]);
           zb[i][M - 1 - k1] = split_inv(b, a, wb[R0 * (M - 1 - k1)]);
         }
-      } else {           // block 0 pairs with itself (and X[MX]), block R0/2 with itself
+      } else {           // block 0 pairs with itself, block R0/2 with itself
+        // slot 0 holds X[0] + i X[MX] (both real): 2 Z[0] = X[0] + X[MX] + i (X[0] - X[MX])
+        za[i][0] = mkc<V>(xa[0].x + xa[0].y, xa[0].x - xa[0].y);
 #pragma unroll
-        for (int k1 = 0; k1 <= M / 2; ++k1) {
-          const int k2 = (M - k1) % M;
-          const V a = xa[k1], b = k1 == 0 ? xm : xa[k2];
+        for (int k1 = 1; k1 <= M / 2; ++k1) {
+          const int k2 = M - k1;
+          const V a = xa[k1], b = xa[k2];
           za[i][k1] = split_inv(a, b, wa[R0 * k1]);
           if (k2 != k1) za[i][k2] = split_inv(b, a, wa[R0 * k2]);
         }
@@ -492,20 +586,25 @@ __device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, Rea
       if constexpr (M > 1) stage_twiddle<R0, M, true>(a, L.twx, it.n1);
       dft_r<R0, true>(a);
 #pragma unroll
-      for (int m = 0; m < R0; ++m) out[i][m] = narrow(a[m]);
+      for (int m = 0; m < R0; ++m) out(i, m, narrow(a[m]));
     }
   }
 }
 
+template <int NX, int NY, int NZ, typename V>
+__device__ __forceinline__ void x_inverse_to_regs(SlabLds<NX, NY, NZ, V>& L, RealRegs<NX, NY, NZ>& out, int tid) {
+  x_inverse_apply(L, tid, [&](int i, int m, float2 v) { out[i][m] = v; });
+}
+
 // Packed real pairs in the register layout -> forward x transform -> rows
-// (natural kx, X[0..MX]); ends with a workgroup barrier (the y pass reads
+// (natural kx, X[0..MX-1], slot 0 holding X[0] + i X[MX]); ends with a workgroup barrier (the y pass reads
 // columns). The first stage writes the LDS slots the same thread read in
 // x_inverse_to_regs, so no barrier is needed before it; otherwise the caller syncs.
 template <int NX, int NY, int NZ, typename V>
 __device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, const RealRegs<NX, NY, NZ>& in,
                                                     int tid) {
   using D = Dims<NX, NY, NZ>;
-  constexpr int R0 = D::RX0, M = D::MXB, MX = D::MX, P = D::PITCH;
+  constexpr int R0 = D::RX0, M = D::MXB, P = D::PITCH;
 #pragma unroll
   for (int i = 0; i < D::IX0; ++i) {
     const RowItem<NX, NY, NZ> it(tid, i);
@@ -520,7 +619,7 @@ __device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, c
     }
   }
   wave_sync();
-  V xa[D::IXP][M], xb[D::IXP][M], xm[D::IXP];
+  V xa[D::IXP][M], xb[D::IXP][M];
 #pragma unroll
   for (int i = 0; i < D::IXP; ++i) {
     const PairItem<NX, NY, NZ> it(tid, i);
@@ -535,8 +634,7 @@ __device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, c
       dft_r<M, false>(zb);
       const V* wa = L.twn + it.ma;   // w^k for k = ma + R0 k1 at wa[R0 k1]
       const V* wb = L.twn + it.mb;
-      // partner Z[MX - k] (for k = 0 it is Z[MX] = Z[0]), two at a time as above
-      xm[i] = mkc<V>(za[0].x - za[0].y, (typename ScalarOf<V>::T)0);
+      // partner Z[MX - k], two at a time as above
       if (it.g != 0) {
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) {
@@ -545,9 +643,11 @@ __device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, c
           xb[i][M - 1 - k1] = split_fwd(b, a, wb[R0 * (M - 1 - k1)]);
         }
       } else {
+        // X[0] = Re Z[0] + Im Z[0] and X[MX] = Re Z[0] - Im Z[0], packed into slot 0
+        xa[i][0] = mkc<V>(za[0].x + za[0].y, za[0].x - za[0].y);
 #pragma unroll
-        for (int k1 = 0; k1 <= M / 2; ++k1) {
-          const int k2 = (M - k1) % M;
+        for (int k1 = 1; k1 <= M / 2; ++k1) {
+          const int k2 = M - k1;
           const V a = za[k1], b = za[k2];
           xa[i][k1] = split_fwd(a, b, wa[R0 * k1]);
           if (k2 != k1) xa[i][k2] = split_fwd(b, a, wa[R0 * k2]);
@@ -572,7 +672,6 @@ __device__ __forceinline__ void x_forward_from_regs(SlabLds<NX, NY, NZ, V>& L, c
         L.S[sidx(it.y, it.ma + R0 * k1, P)] = xa[i][k1];
         L.S[sidx(it.y, it.mb + R0 * k1, P)] = xb[i][k1];
       }
-      if (it.g == 0) L.S[sidx(it.y, MX, P)] = xm[i];
     }
   }
   __syncthreads();
@@ -962,7 +1061,7 @@ __device__ __forceinline__ void u_c2r_update(SlabLds<NX, NY, NZ, V>& L, const fl
   const auto& tab = TabSel<V>::get(t);
   const int mode = ADJ || xi == 2 ? 0 : xi + 1;
   float2* u = reinterpret_cast<float2*>(B.u[xi]) + (size_t)z * D::SLAB_P;
-  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+  YRegs<NX, NY, NZ> ry;
   y_load<NX, NY, NZ>(ry, src + (size_t)z * D::SLAB_C, tid);
   float2 uo[D::IX0][D::RX0];
   if (ADJ || !init) load_real<NX, NY, NZ>(uo, u, tid);   // in flight during the transform
@@ -1066,30 +1165,23 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* H0, cons
     // passes are recomputed per component instead of being kept live across the loop
     int tl = tid;
     asm volatile("" : "+v"(tl));
-    float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+    YRegs<NX, NY, NZ> ry;
     y_load<NX, NY, NZ>(ry, H + cz, tl);
     __syncthreads();   // tables (first pass) / previous pass done with S
     y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tl);
     float2 ro[D::IX0][D::RX0];
     load_real<NX, NY, NZ>(ro, r, tl);   // in flight during the x pass
-    float2 h[D::IX0][D::RX0];
-    x_inverse_to_regs(L, h, tl);
-#pragma unroll
-    for (int i = 0; i < D::IX0; ++i) {
+    // rho update as the inverse transform's values come out (no array of them)
+    x_inverse_apply(L, tl, [&](int i, int m, float2 h) {
       const RowItem<NX, NY, NZ> it(tl, i);
-      if (it.ok) {
-#pragma unroll
-        for (int m = 0; m < D::RX0; ++m) {
-          const int n = it.n(m);
-          float b0, b1;
-          if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
-          else if (xi == 1) { b0 = b1 = L.py[it.y]; }
-          else { b0 = b1 = bzz; }
-          r[it.pair(m)] = make_float2(b0 * (b0 * ro[i][m].x - sc.dt_rho0 * h[i][m].x),
-                                      b1 * (b1 * ro[i][m].y - sc.dt_rho0 * h[i][m].y));
-        }
-      }
-    }
+      const int n = it.n(m);
+      float b0, b1;
+      if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
+      else if (xi == 1) { b0 = b1 = L.py[it.y]; }
+      else { b0 = b1 = bzz; }
+      r[it.pair(m)] = make_float2(b0 * (b0 * ro[i][m].x - sc.dt_rho0 * h.x),
+                                  b1 * (b1 * ro[i][m].y - sc.dt_rho0 * h.y));
+    });
   }
   float2 p[D::IX0][D::RX0], r1[D::IX0][D::RX0];
   load_real<NX, NY, NZ>(p, reinterpret_cast<const float2*>(B.rho[xi0]) + rz, tid);
@@ -1287,7 +1379,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_rho(const float2* __restri
   const int z = blockIdx.x >> 1, half = blockIdx.x & 1, tid = threadIdx.x;
   const int xi0 = half == 0 ? 0 : 2, nxi = half == 0 ? 2 : 1;
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
-  float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+  YRegs<NX, NY, NZ> ry;
   y_load<NX, NY, NZ>(ry, Qs + cz, tid);
   float2 src[D::IX0][D::RX0];
   if (z == 0) load_real<NX, NY, NZ>(src, reinterpret_cast<const float2*>(yplane), tid);   // data source
@@ -1349,7 +1441,7 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __rest
   const size_t cz = (size_t)z * D::SLAB_C, rz = (size_t)z * D::SLAB_P;
   float2 g[D::IX0][D::RX0];
   if (with_velocity) {
-    float2 ry[YItems<NX, NY, NZ>::I1 + 1][D::MYB];
+    YRegs<NX, NY, NZ> ry;
     y_load<NX, NY, NZ>(ry, Qs + cz, tid);
     load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
     __syncthreads();

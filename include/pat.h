@@ -107,6 +107,19 @@ pat_status pat_plan_set_stream(pat_plan* plan, void* stream);
  * and spectra are FP32 in both cases. */
 pat_status pat_plan_set_fft_precision(pat_plan* plan, int32_t bits);
 
+/* Which implementation of the propagator A, A^T (Sec. 4.3) the plan runs;
+ * both compute the same operator.
+ *  PAT_SCHEME_SLAB: per time step, 2D slab transforms fused with the state
+ *    updates and z-pencil passes fused with the k-space multipliers;
+ *  PAT_SCHEME_LINE (default where built: cubic grids): every field component
+ *    kept real along its own axis and transformed along the other two, so a
+ *    time step is one launch of independent 1D lines (four transforms per
+ *    line). It needs FP64 butterflies; with pat_plan_set_fft_precision(32)
+ *    the slab scheme runs. Returns PAT_ERR_UNSUPPORTED when the grid has no
+ *    line propagator. */
+typedef enum { PAT_SCHEME_SLAB = 0, PAT_SCHEME_LINE = 1 } pat_scheme;
+pat_status pat_plan_set_scheme(pat_plan* plan, int32_t scheme);
+
 /* f = C A p0 (eq. Fwd without noise). p0: device [nz][ny][nx]; f: device [nt][mc].
  * p0 and f must not overlap. */
 pat_status pat_forward(pat_plan* plan, const float* p0, float* f);
@@ -196,7 +209,9 @@ typedef enum {
   PAT_K_ADJ_U = 5,      /* adjoint: slab pass, velocity update and its 2D FFT (per component) */
   PAT_K_ZDIV_SUM = 6,   /* adjoint: z pass of the summed divergence (3 in, 1 out) */
   PAT_K_ADJ_RHO = 7,    /* adjoint: slab pass, density update with the data source, 2D FFT */
-  PAT_K_COUNT = 8
+  PAT_K_LINE_FWD = 8,   /* line scheme: one forward time step of all three components */
+  PAT_K_LINE_ADJ = 9,   /* line scheme: one adjoint time step of all three components */
+  PAT_K_COUNT = 10
 } pat_kernel_id;
 
 pat_status pat_profile_begin(pat_plan* plan, int32_t kernel_id, int32_t max_launches);

@@ -17,6 +17,7 @@
 #include "sample_common.hpp"
 #include "vec_common.hpp"
 #include "wave_common.hpp"
+#include "line_common.hpp"
 
 namespace pat {
 
@@ -40,6 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t u[3], rho[3], spec[4], planes2, planes, red_partial, red_out, flags;
+  size_t lsu[3], lsr[3], lhub[2][3], lplanes, lspec;   // line propagator
   size_t img[7], dual, data[6];
   size_t total;
 };
@@ -68,6 +70,12 @@ Layout make_layout(const pat_grid& g, const pat_sampling& s) {
   L.red_partial = take(kRedBlocks * sizeof(double));
   L.red_out = take(kRedSlots * sizeof(double));
   L.flags = take((size_t)g.nz * sizeof(unsigned));
+  for (int i = 0; i < 3; ++i) L.lsu[i] = take(C);
+  for (int i = 0; i < 3; ++i) L.lsr[i] = take(C);
+  for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 3; ++i) L.lhub[j][i] = take(C);
+  L.lplanes = take((size_t)g.nt * (g.nx / 2 + 1) * g.ny * sizeof(float2));
+  L.lspec = take(C);
   for (int i = 0; i < 7; ++i) L.img[i] = take(R);
   L.dual = take(n_dual(g, 1) * sizeof(float));
   const size_t D = (size_t)g.nt * s.mc * sizeof(float);
@@ -194,6 +202,11 @@ struct pat_plan {
   float* dual;
   float* data[6];
   int fftp;                 // FftPrecision of the propagator kernels
+  const LineImpl* limpl;    // line propagator of this size (cubic grids), or null
+  int scheme;               // PAT_SCHEME_*: which propagator runs (the line one needs FP64)
+  LineTables ltabs;
+  LineScalars lsc;
+  LineBuffers lb;
   KernelTimer timer;        // active when timer.ev != nullptr
   std::vector<hipEvent_t> timer_events;
   std::vector<int> timer_ids;
@@ -236,7 +249,14 @@ pat_status build_tables(pat_plan* P, const pat_sampling* s) {
   };
   const size_t o_mpy = axis_mult(NY, +1), o_mmy = axis_mult(NY, -1);
   const size_t o_mpz = axis_mult(NZ, +1), o_mmz = axis_mult(NZ, -1);
+  // line propagator: multipliers and sinc arguments by natural frequency index (cubic grid)
+  const size_t o_lmp = c2.size();
+  for (int k = 0; k < NX; ++k) c2.push_back(deriv(k, NX, +1));
+  const size_t o_lmm = c2.size();
+  for (int k = 0; k < NX; ++k) c2.push_back(deriv(k, NX, -1));
   const double hs = g.c0 * g.dt / 2.0;
+  const size_t o_lh = r.size();
+  for (int k = 0; k < NX; ++k) r.push_back(hs * wavenumber(k, NX, g.dx));
   const size_t o_hx = r.size();
   for (int kx = 0; kx < NKX; ++kx) r.push_back(hs * wavenumber(kx, NX, g.dx));
   const size_t o_hy = r.size();
@@ -313,6 +333,26 @@ pat_status build_tables(pat_plan* P, const pat_sampling* s) {
   P->inv = s->kind == PAT_SAMPLE_POINTS ? di + o_inv : nullptr;
   P->perm = s->kind == PAT_SAMPLE_HADAMARD ? di + o_perm : nullptr;
   P->invperm = s->kind == PAT_SAMPLE_HADAMARD ? di + o_invperm : nullptr;
+  {
+    LineTables& lt = P->ltabs;
+    const double2* dc = reinterpret_cast<const double2*>(p_cd);
+    const double* dr = reinterpret_cast<const double*>(p_rd);
+    lt.mp = dc + o_lmp;
+    lt.mm = dc + o_lmm;
+    lt.h = dr + o_lh;
+    lt.tw = dc + o_twz;
+    lt.a[0] = t.ax; lt.a[1] = t.ay; lt.a[2] = t.az;
+    lt.b[0] = t.bx; lt.b[1] = t.by; lt.b[2] = t.bz;
+    LineScalars& ls = P->lsc;
+    ls.c2 = g.c0 * g.c0;
+    ls.dt_over_rho0 = g.dt / g.rho0;
+    ls.dt_rho0 = g.dt * g.rho0;
+    ls.half_dt_over_rho0 = g.dt / (2.0 * g.rho0);
+    ls.inv_3c2 = 1.0 / (3.0 * g.c0 * g.c0);
+    ls.inv_n = 1.0 / NX;
+    ls.inv_ntot = 1.0 / ((double)NX * NY * NZ);
+    ls.adj_scale = g.c0 * g.c0 * g.dt / g.rho0;
+  }
   WaveScalars& sc = P->sc;
   sc.dt_over_rho0 = (float)(g.dt / g.rho0);
   sc.dt_rho0 = (float)(g.dt * g.rho0);
@@ -335,12 +375,19 @@ long vol_n(const pat_plan* P) { return (long)n_voxels(P->g); }
 long data_n(const pat_plan* P) { return (long)P->g.nt * P->mc; }
 
 // ---- operator pieces used by the entry points and the solver ----------------
+bool use_line(const pat_plan* P) { return P->scheme == PAT_SCHEME_LINE && P->limpl && P->fftp == FFT_FP64; }
+
 pat_status op_forward(pat_plan* P, const float* p0, float* f) {
   float* planes = P->kind == PAT_SAMPLE_FULL ? f : P->planes;
   const long nplane = (long)P->g.nt * P->npix;
-  PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, P->planes2, P->g.nt, P->stream,
-                                        P->timer.ev ? &P->timer : nullptr, P->handoff));
-  PAT_TRY_HIP(launch_sum2(P->planes2, nplane, planes, nplane, P->stream));
+  KernelTimer* kt = P->timer.ev ? &P->timer : nullptr;
+  if (use_line(P)) {
+    PAT_TRY_HIP(P->limpl->forward(P->ltabs, P->lsc, P->lb, P->tabs, p0, planes, P->g.nt, P->stream, kt));
+  } else {
+    PAT_TRY_HIP(P->impl->forward[P->fftp](P->tabs, P->sc, P->wb, p0, P->planes2, P->g.nt, P->stream, kt,
+                                          P->handoff));
+    PAT_TRY_HIP(launch_sum2(P->planes2, nplane, planes, nplane, P->stream));
+  }
   if (P->kind == PAT_SAMPLE_POINTS)
     PAT_TRY_HIP(launch_rsp_gather(planes, P->idx, f, P->npix, P->mc, P->g.nt, P->stream));
   else if (P->kind == PAT_SAMPLE_HADAMARD)
@@ -357,8 +404,11 @@ pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
     PAT_TRY_HIP(launch_shd_adjoint(f, P->invperm, P->idx, P->planes, P->npix, P->mc, P->g.nt, P->stream));
     planes = P->planes;
   }
-  PAT_TRY_HIP(P->impl->adjoint[P->fftp](P->tabs, P->sc, P->wb, planes, p, P->g.nt, P->stream,
-                                        P->timer.ev ? &P->timer : nullptr, P->handoff));
+  KernelTimer* kt = P->timer.ev ? &P->timer : nullptr;
+  if (use_line(P))
+    PAT_TRY_HIP(P->limpl->adjoint(P->ltabs, P->lsc, P->lb, P->tabs, planes, p, P->g.nt, P->stream, kt));
+  else
+    PAT_TRY_HIP(P->impl->adjoint[P->fftp](P->tabs, P->sc, P->wb, planes, p, P->g.nt, P->stream, kt, P->handoff));
   return PAT_OK;
 }
 
@@ -457,6 +507,8 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
   P->stream = static_cast<hipStream_t>(stream);
   P->impl = find_wave_impl(grid->nx, grid->ny, grid->nz);
   P->fftp = FFT_FP64;
+  P->limpl = find_line_impl(grid->nx, grid->ny, grid->nz);
+  P->scheme = P->limpl ? PAT_SCHEME_LINE : PAT_SCHEME_SLAB;
   if (hipGetDevice(&P->device) != hipSuccess) {
     delete P;
     return set_error(PAT_ERR_HIP, "hipGetDevice failed (no GPU?)");
@@ -474,6 +526,13 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
     P->wb.rho[i] = ws_ptr<float>(P, L.rho[i]);
   }
   for (int i = 0; i < 4; ++i) P->wb.spec[i] = ws_ptr<float2>(P, L.spec[i]);
+  for (int i = 0; i < 3; ++i) {
+    P->lb.su[i] = ws_ptr<float2>(P, L.lsu[i]);
+    P->lb.sr[i] = ws_ptr<float2>(P, L.lsr[i]);
+    for (int j = 0; j < 2; ++j) P->lb.hub[j][i] = ws_ptr<float2>(P, L.lhub[j][i]);
+  }
+  P->lb.planes = ws_ptr<float2>(P, L.lplanes);
+  P->lb.spec = ws_ptr<float2>(P, L.lspec);
   P->planes2 = ws_ptr<float>(P, L.planes2);
   P->planes = smp->kind == PAT_SAMPLE_FULL ? nullptr : ws_ptr<float>(P, L.planes);
   P->red_partial = ws_ptr<double>(P, L.red_partial);
@@ -519,6 +578,16 @@ pat_status pat_plan_set_fft_precision(pat_plan* plan, int32_t bits) {
   PAT_TRY(check_plan(plan));
   if (bits != 32 && bits != 64) return set_error(PAT_ERR_INVALID, "pat_plan_set_fft_precision: bits must be 32 or 64");
   plan->fftp = bits == 64 ? FFT_FP64 : FFT_FP32;
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_scheme(pat_plan* plan, int32_t scheme) {
+  PAT_TRY(check_plan(plan));
+  if (scheme != PAT_SCHEME_SLAB && scheme != PAT_SCHEME_LINE)
+    return set_error(PAT_ERR_INVALID, "pat_plan_set_scheme: unknown scheme %d", (int)scheme);
+  if (scheme == PAT_SCHEME_LINE && !plan->limpl)
+    return set_error(PAT_ERR_UNSUPPORTED, "pat_plan_set_scheme: no line propagator for this grid");
+  plan->scheme = scheme;
   return PAT_OK;
 }
 
@@ -805,11 +874,13 @@ pat_status pat_profile_end(pat_plan* plan, double* total_ms, int32_t* launches) 
 }
 
 pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char** name, double* bytes_per_launch) {
-  static const char* kNames[K_COUNT] = {"k_zgrad", "k_fwd_u", "k_zmul<div>", "k_fwd_rho",
-                                        "k_zmul<grad>", "k_adj_u", "k_zdiv_sum", "k_adj_rho"};
-  // algorithmic HBM bytes per launch in units of C (one slab-spectrum field) and R (one real field)
-  static const int kC[K_COUNT] = {4, 5, 6, 5, 6, 6, 4, 4};
-  static const int kR[K_COUNT] = {0, 6, 0, 6, 0, 6, 0, 6};
+  static const char* kNames[K_COUNT] = {"k_zgrad", "k_fwd_u",   "k_zmul<div>", "k_fwd_rho", "k_zmul<grad>",
+                                        "k_adj_u", "k_zdiv_sum", "k_adj_rho",   "k_line<fwd>", "k_line<adj>"};
+  // algorithmic HBM bytes per launch in units of C (one slab-spectrum field) and R (one real field);
+  // a line step reads the three hub spectra and both states and writes both states and its output,
+  // for each of the three components
+  static const int kC[K_COUNT] = {4, 5, 6, 5, 6, 6, 4, 4, 24, 24};
+  static const int kR[K_COUNT] = {0, 6, 0, 6, 0, 6, 0, 6, 0, 0};
   PAT_TRY(check_plan(plan));
   if (kernel_id < 0 || kernel_id >= K_COUNT) return set_error(PAT_ERR_INVALID, "pat_kernel_info: bad kernel_id");
   const double C = (double)n_spec(plan->g) * sizeof(float2), R = (double)n_voxels(plan->g) * sizeof(float);

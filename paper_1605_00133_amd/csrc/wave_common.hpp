@@ -67,7 +67,9 @@ enum KernelId {
   K_ADJ_U = 5,      // adjoint slab pass: velocity update + R2C (per component)
   K_ZDIV_SUM = 6,   // adjoint pencil pass of the summed divergence (3 in, 1 out)
   K_ADJ_RHO = 7,    // adjoint slab pass: density update + source + R2C (two halves per slab)
-  K_COUNT = 8
+  K_LINE_FWD = 8,   // line propagator: one forward time step of all three components
+  K_LINE_ADJ = 9,   // line propagator: one adjoint time step
+  K_COUNT = 10
 };
 
 // Optional HIP-event bracketing of kernel launches (which = id, or -2 for all).
@@ -78,6 +80,19 @@ struct KernelTimer {
   int cap;
   int count;
 };
+
+// Runs launch(), bracketed by timer events when kernel id is being recorded.
+template <typename F>
+inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
+  const bool on = kt && (kt->which == id || kt->which == -2) && kt->count < kt->cap;
+  if (on) (void)hipEventRecord(kt->ev[2 * kt->count], st);
+  launch();
+  if (on) {
+    (void)hipEventRecord(kt->ev[2 * kt->count + 1], st);
+    kt->ids[kt->count] = id;
+    kt->count++;
+  }
+}
 
 // Hand-off flags of the slab-pair velocity passes (device, >= nz entries, zero
 // at plan creation) and the host-side launch epoch that tags them.

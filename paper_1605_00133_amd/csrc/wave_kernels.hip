@@ -40,13 +40,13 @@
 
 #include "fft_radix.hpp"
 #include "wave_common.hpp"
+#include "kspace.hpp"
+#include "line_common.hpp"
 
 namespace pat {
 
 constexpr int kThreadsZ = 256;
 constexpr int kThreadsSlab = 512;
-
-__host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Slot of row index idx in an LDS slab row: one pad slot after every 8. With
 // a row pitch = 1 mod 8, 8 lanes that touch 8 consecutive indices of one row,
@@ -101,32 +101,6 @@ template <> struct TabSel<float2> {
 template <> struct TabSel<double2> {
   static __device__ __forceinline__ const SpecTables<double2, double>& get(const WaveTables& t) { return t.d; }
 };
-
-// sinc(sqrt(s)) = sin(h)/h at h^2 = s
-__device__ __forceinline__ float sinc_of_sq(float s) {
-  const float h = sqrtf(s);
-  return h > 0.f ? sinf(h) / h : 1.f;
-}
-__device__ __forceinline__ double sinc_of_sq(double s) {
-  if (s < 2.5) {
-    // Taylor series sum_k (-s)^k / (2k+1)!, truncated after k = 12 (< 4e-21 at s = 2.5)
-    double r = 1.0 / 15511210043330985984000000.0;
-    r = r * -s + 1.0 / 25852016738884976640000.0;
-    r = r * -s + 1.0 / 51090942171709440000.0;
-    r = r * -s + 1.0 / 121645100408832000.0;
-    r = r * -s + 1.0 / 355687428096000.0;
-    r = r * -s + 1.0 / 1307674368000.0;
-    r = r * -s + 1.0 / 6227020800.0;
-    r = r * -s + 1.0 / 39916800.0;
-    r = r * -s + 1.0 / 362880.0;
-    r = r * -s + 1.0 / 5040.0;
-    r = r * -s + 1.0 / 120.0;
-    r = r * -s + 1.0 / 6.0;
-    return r * -s + 1.0;
-  }
-  const double h = sqrt(s);
-  return sin(h) / h;
-}
 
 // ---- LDS workspace of a slab workgroup ---------------------------------------
 // S holds the slab as rows y (0..NY-1) of PITCH complex slots; index idx of a
@@ -1471,23 +1445,87 @@ __global__ __launch_bounds__(kThreadsSlab) void k_adj_final(const float2* __rest
   }
 }
 
+// ---- plain batched slab transforms (used by the line propagator) -----------------
+
+// out[b] = scale * R2C_xy(in[b]) for slab b = blockIdx.x: real [NY][NX] -> [NX/2+1][ky_pos].
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(kThreadsSlab) void k_slab_r2c(const float* __restrict__ in, float2* out, float scale,
+                                                           WaveTables t) {
+  using D = Dims<NX, NY, NZ>;
+  __shared__ SlabLds<NX, NY, NZ, V> L;
+  const int tid = threadIdx.x;
+  const size_t b = blockIdx.x;
+  load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
+  float2 v[D::IX0][D::RX0];
+  load_real<NX, NY, NZ>(v, reinterpret_cast<const float2*>(in) + b * D::SLAB_P, tid);
+#pragma unroll
+  for (int i = 0; i < D::IX0; ++i)
+#pragma unroll
+    for (int m = 0; m < D::RX0; ++m) v[i][m] = make_float2(v[i][m].x * scale, v[i][m].y * scale);
+  __syncthreads();
+  x_forward_from_regs(L, v, tid);
+  y_forward_to_global(L, out + b * D::SLAB_C, TabSel<V>::get(t).tw_y, tid);
+}
+
+// out[b] = scale * C2R_xy(in[b]) (unnormalised inverse) for slab b = blockIdx.x.
+template <int NX, int NY, int NZ, typename V>
+__global__ __launch_bounds__(kThreadsSlab) void k_slab_c2r(const float2* __restrict__ in, float* out, float scale,
+                                                           WaveTables t) {
+  using D = Dims<NX, NY, NZ>;
+  __shared__ SlabLds<NX, NY, NZ, V> L;
+  const int tid = threadIdx.x;
+  const size_t b = blockIdx.x;
+  YRegs<NX, NY, NZ> ry;
+  y_load<NX, NY, NZ>(ry, in + b * D::SLAB_C, tid);
+  load_slab_tables(L, t, nullptr, nullptr, (const V*)nullptr, 0, tid);
+  __syncthreads();
+  y_inverse(L, ry, 0, TabSel<V>::get(t).tw_y, tid);
+  float2* o = reinterpret_cast<float2*>(out) + b * D::SLAB_P;
+  x_inverse_apply(L, tid, [&](int i, int m, float2 v) {
+    const RowItem<NX, NY, NZ> it(tid, i);
+    o[it.pair(m)] = make_float2(v.x * scale, v.y * scale);
+  });
+}
+
+template <int N>
+hipError_t slab_r2c_n(const float* in, float2* out, int nb, float scale, const WaveTables& t, hipStream_t st) {
+  k_slab_r2c<N, N, N, double2><<<nb, kThreadsSlab, 0, st>>>(in, out, scale, t);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t slab_c2r_n(const float2* in, float* out, int nb, float scale, const WaveTables& t, hipStream_t st) {
+  k_slab_c2r<N, N, N, double2><<<nb, kThreadsSlab, 0, st>>>(in, out, scale, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_r2c(int n, const float* in, float2* out, int nb, float scale, const WaveTables& t,
+                           hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  switch (n) {
+    case 16: return slab_r2c_n<16>(in, out, nb, scale, t, st);
+    case 32: return slab_r2c_n<32>(in, out, nb, scale, t, st);
+    case 64: return slab_r2c_n<64>(in, out, nb, scale, t, st);
+    case 128: return slab_r2c_n<128>(in, out, nb, scale, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_slab_c2r(int n, const float2* in, float* out, int nb, float scale, const WaveTables& t,
+                           hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  switch (n) {
+    case 16: return slab_c2r_n<16>(in, out, nb, scale, t, st);
+    case 32: return slab_c2r_n<32>(in, out, nb, scale, t, st);
+    case 64: return slab_c2r_n<64>(in, out, nb, scale, t, st);
+    case 128: return slab_c2r_n<128>(in, out, nb, scale, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ---- launch sequences ----------------------------------------------------------
 
 inline unsigned next_epoch(HandOff& ho) {   // never 0, the value of a cleared flag
   if (++ho.epoch == 0) ho.epoch = 1;
   return ho.epoch;
-}
-
-template <typename F>
-inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
-  const bool on = kt && (kt->which == id || kt->which == -2) && kt->count < kt->cap;
-  if (on) (void)hipEventRecord(kt->ev[2 * kt->count], st);
-  launch();
-  if (on) {
-    (void)hipEventRecord(kt->ev[2 * kt->count + 1], st);
-    kt->ids[kt->count] = id;
-    kt->count++;
-  }
 }
 
 template <int NX, int NY, int NZ, typename V>

@@ -61,6 +61,7 @@ SIGNATURES = {
     "pat_plan_destroy": (C.c_int, [_P]),
     "pat_plan_set_stream": (C.c_int, [_P, _P]),
     "pat_plan_set_fft_precision": (C.c_int, [_P, C.c_int32]),
+    "pat_plan_set_scheme": (C.c_int, [_P, C.c_int32]),
     "pat_forward": (C.c_int, [_P, _P, _P]),
     "pat_adjoint": (C.c_int, [_P, _P, _P]),
     "pat_sample": (C.c_int, [_P, _P, _P]),
@@ -195,6 +196,12 @@ class Plan:
     def set_fft_precision(self, bits):
         _check(lib().pat_plan_set_fft_precision(self.handle, int(bits)))
 
+    def set_scheme(self, scheme):
+        """PAT_SCHEME_LINE (default on cubic grids) or PAT_SCHEME_SLAB; the names "line"/"slab" work too."""
+        if isinstance(scheme, str):
+            scheme = {"slab": PAT_SCHEME_SLAB, "line": PAT_SCHEME_LINE}[scheme]
+        _check(lib().pat_plan_set_scheme(self.handle, int(scheme)))
+
     def sync_stream(self):
         stream = self.torch.cuda.current_stream(self.device).cuda_stream
         _check(lib().pat_plan_set_stream(self.handle, C.c_void_p(stream)))
@@ -271,7 +278,11 @@ def pat_power_iteration(plan, x0, n_iter):
     return out.value
 
 
-PAT_K_COUNT = 8
+PAT_K_COUNT = 10
+PAT_K_LINE_FWD = 8
+PAT_K_LINE_ADJ = 9
+PAT_SCHEME_SLAB = 0
+PAT_SCHEME_LINE = 1
 
 
 def pat_profile_begin(plan, kernel_id=-2, max_launches=8192):
@@ -279,7 +290,7 @@ def pat_profile_begin(plan, kernel_id=-2, max_launches=8192):
 
 
 def pat_profile_end(plan):
-    """Returns (total_ms[8], launches[8]) as numpy arrays."""
+    """Returns (total_ms[PAT_K_COUNT], launches[PAT_K_COUNT]) as numpy arrays."""
     tot = (C.c_double * PAT_K_COUNT)()
     cnt = (C.c_int32 * PAT_K_COUNT)()
     _check(lib().pat_profile_end(plan.handle, tot, cnt))

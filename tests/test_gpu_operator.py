@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 TOL_OP = 1e-5
 
 
-def _fwd_case(n, nt, kind, pml=8, x=None, bits=64):
+def _fwd_case(n, nt, kind, pml=8, x=None, bits=64, scheme="line"):
     g = oracle_grid(n, nt, pml)
     smp = oracle_sampling(kind, n)
     x = phantom(n, pml) if x is None else x
@@ -25,12 +25,13 @@ def _fwd_case(n, nt, kind, pml=8, x=None, bits=64):
     from paper_1605_00133_amd import pat as P
     plan = gpu_plan(n, nt, smp, pml)
     plan.set_fft_precision(bits)
+    plan.set_scheme(scheme)
     f = empty(plan.data_shape)
     P.pat_forward(plan, to_dev(x), f)
     return to_host(f), ref
 
 
-def _adj_case(n, nt, kind, pml=8, seed=5, bits=64):
+def _adj_case(n, nt, kind, pml=8, seed=5, bits=64, scheme="line"):
     g = oracle_grid(n, nt, pml)
     smp = oracle_sampling(kind, n)
     y = gaussian_data((nt, smp.mc), seed)
@@ -38,26 +39,31 @@ def _adj_case(n, nt, kind, pml=8, seed=5, bits=64):
     from paper_1605_00133_amd import pat as P
     plan = gpu_plan(n, nt, smp, pml)
     plan.set_fft_precision(bits)
+    plan.set_scheme(scheme)
     p = empty(plan.vol_shape)
     P.pat_adjoint(plan, to_dev(y), p)
     return to_host(p), ref
 
 
-@pytest.mark.parametrize("n,nt,kind,pml", [(16, 40, "full", 4), (32, 190, "points", 8), (32, 190, "hadamard", 8),
-                                           (32, 190, "full", 8)])
-def test_forward_matches_oracle(n, nt, kind, pml):
-    got, ref = _fwd_case(n, nt, kind, pml)
+CASES = [(16, 40, "full", 4), (32, 190, "points", 8), (32, 190, "hadamard", 8), (32, 190, "full", 8),
+         (64, 24, "points", 8)]
+
+
+@pytest.mark.parametrize("scheme", ["line", "slab"])
+@pytest.mark.parametrize("n,nt,kind,pml", CASES)
+def test_forward_matches_oracle(n, nt, kind, pml, scheme):
+    got, ref = _fwd_case(n, nt, kind, pml, scheme=scheme)
     err = rel_l2(got, ref)
-    print(f"forward {n}^3 nt={nt} {kind}: rel L2 vs FP64 = {err:.3e}")
+    print(f"forward {n}^3 nt={nt} {kind} {scheme}: rel L2 vs FP64 = {err:.3e}")
     assert err < TOL_OP
 
 
-@pytest.mark.parametrize("n,nt,kind,pml", [(16, 40, "full", 4), (32, 190, "points", 8), (32, 190, "hadamard", 8),
-                                           (32, 190, "full", 8)])
-def test_adjoint_matches_oracle(n, nt, kind, pml):
-    got, ref = _adj_case(n, nt, kind, pml)
+@pytest.mark.parametrize("scheme", ["line", "slab"])
+@pytest.mark.parametrize("n,nt,kind,pml", CASES)
+def test_adjoint_matches_oracle(n, nt, kind, pml, scheme):
+    got, ref = _adj_case(n, nt, kind, pml, scheme=scheme)
     err = rel_l2(got, ref)
-    print(f"adjoint {n}^3 nt={nt} {kind}: rel L2 vs FP64 = {err:.3e}")
+    print(f"adjoint {n}^3 nt={nt} {kind} {scheme}: rel L2 vs FP64 = {err:.3e}")
     assert err < TOL_OP
 
 
@@ -72,24 +78,28 @@ def test_fp32_butterfly_variant(kind):
     assert e1 < TOL_OP and e2 < TOL_OP
 
 
-def test_forward_without_pml_closed_form_random_input():
+@pytest.mark.parametrize("scheme", ["line", "slab"])
+def test_forward_without_pml_closed_form_random_input(scheme):
     """P = 0 and white-noise p0 excite every mode including the Nyquist planes."""
     n, nt = 32, 60
     x = gaussian_volume((n, n, n), 3)
-    got, ref = _fwd_case(n, nt, "full", pml=0, x=x)
+    got, ref = _fwd_case(n, nt, "full", pml=0, x=x, scheme=scheme)
     err = rel_l2(got, ref)
     print(f"forward 32^3 no PML white noise: rel L2 = {err:.3e}")
     assert err < TOL_OP
 
 
+@pytest.mark.parametrize("scheme", ["line", "slab"])
 @pytest.mark.parametrize("nt", [1, 2, 3])
-def test_short_series_edge_cases(nt):
+def test_short_series_edge_cases(nt, scheme):
     """Nt = 1 (no time step: plane of p0 only), 2 and 3, with a volume that is nonzero on the plane."""
     x = gaussian_volume((32, 32, 32), 13)
-    got, ref = _fwd_case(32, nt, "points", x=x)
-    assert rel_l2(got, ref) < TOL_OP
-    got, ref = _adj_case(32, nt, "points")
-    assert rel_l2(got, ref) < TOL_OP
+    got, ref = _fwd_case(32, nt, "points", x=x, scheme=scheme)
+    e1 = rel_l2(got, ref)
+    got, ref = _adj_case(32, nt, "points", scheme=scheme)
+    e2 = rel_l2(got, ref)
+    print(f"Nt = {nt} {scheme}: forward {e1:.3e}, adjoint {e2:.3e}")
+    assert e1 < TOL_OP and e2 < TOL_OP
 
 
 def test_64_cubed_forward_adjoint():
@@ -101,13 +111,15 @@ def test_64_cubed_forward_adjoint():
     assert e1 < TOL_OP and e2 < TOL_OP
 
 
+@pytest.mark.parametrize("scheme", ["line", "slab"])
 @pytest.mark.parametrize("kind", ["points", "hadamard", "full"])
-def test_gpu_adjoint_identity(kind):
-    """<C A x, y> = <x, A^T C^T y> on the GPU itself (FP32 arithmetic, FP64 dot products)."""
+def test_gpu_adjoint_identity(kind, scheme):
+    """<C A x, y> = <x, A^T C^T y> on the GPU itself (FP32 storage, FP64 dot products)."""
     from paper_1605_00133_amd import pat as P
     n, nt = 32, 120
     smp = oracle_sampling(kind, n)
     plan = gpu_plan(n, nt, smp)
+    plan.set_scheme(scheme)
     x = gaussian_volume((n, n, n), 11)
     y = gaussian_data((nt, smp.mc), 12)
     f = empty(plan.data_shape)
@@ -120,7 +132,7 @@ def test_gpu_adjoint_identity(kind):
     # random vectors make <CAx, y> small by chance; scale by the Cauchy-Schwarz bound instead
     scale = np.linalg.norm(fh) * np.linalg.norm(y)
     rel = abs(lhs - rhs) / scale
-    print(f"GPU adjoint identity {kind}: |lhs-rhs|/(|CAx||y|) = {rel:.3e}, |lhs-rhs|/|lhs| = {abs(lhs - rhs) / abs(lhs):.3e}")
+    print(f"GPU adjoint identity {kind} {scheme}: |lhs-rhs|/(|CAx||y|) = {rel:.3e}, |lhs-rhs|/|lhs| = {abs(lhs - rhs) / abs(lhs):.3e}")
     assert rel < 1e-6
 
 

@@ -47,7 +47,8 @@ def code_only(text):
 def kernel_source_hash(read=None):
     """Hash of the propagator kernel sources (code only)."""
     h = hashlib.sha256()
-    for f in ("wave_kernels.hip", "fft_radix.hpp", "wave_common.hpp"):
+    for f in ("line_kernels.hip", "line_common.hpp", "kspace.hpp", "wave_kernels.hip", "fft_radix.hpp",
+              "wave_common.hpp"):
         path = os.path.join(ROOT, "paper_1605_00133_amd", "csrc", f)
         text = read(f) if read else open(path, encoding="utf-8").read()
         h.update(code_only(text).encode())
@@ -177,6 +178,8 @@ def main():
     tot_ms, launches = P.pat_profile_end(plan)
     kernels = {}
     for k in range(P.PAT_K_COUNT):
+        if launches[k] == 0:   # kernels of the scheme that is not running
+            continue
         name, nbytes = P.pat_kernel_info(plan, k)
         avg = tot_ms[k] / max(1, launches[k])
         kernels[name] = {"avg_us": round(avg * 1e3, 3), "launches": int(launches[k]),

@@ -14,6 +14,8 @@
 // the stage-1 layout, where it holds frequencies. HBM traffic per component and
 // step: the hub (three component spectra, summed in FP64), both states in and
 // out, and the output spectrum, each 8 (N/2+1) N^2 bytes.
+#include <type_traits>
+
 #include "fft_radix.hpp"
 #include "kspace.hpp"
 #include "line_common.hpp"
@@ -34,10 +36,38 @@ struct LD {
   static_assert(N % kLT == 0 && NL % kLT == 0, "a tile is 16 lines");
 };
 
+#ifndef PAT_LINE_LDS_F32
+#define PAT_LINE_LDS_F32 0
+#endif
+constexpr bool kTF32 = PAT_LINE_LDS_F32 != 0;
+#ifndef PAT_LINE_WAVES
+#define PAT_LINE_WAVES 2
+#endif
+using TStore = std::conditional_t<kTF32, float2, double2>;
+
+// Per-block copy of the small tables (LDS), so the phases after the first
+// read them without a global round trip.
+struct LTab {
+  const double* h;     // (c0 dt / 2) k by natural index
+  const double2* mp;   // i k exp(+i k dx/2)
+  const double2* mm;   // i k exp(-i k dx/2)
+  const double2* tw;   // exp(-2 pi i j / N)
+  const float* a;      // PML factors of this block's axis
+  const float* b;
+};
+
 template <int N>
 struct LineLds {
-  double2 T[N * kLT];   // value of tile line l at point (or position) j: T[j * 16 + l]
+  TStore T[N * kLT];   // value of tile line l at point (or position) j: T[j * 16 + l]
+  double h[N];
+  double2 mp[N], mm[N], tw[N];
+  float a[N], b[N];
 };
+
+__device__ __forceinline__ void tput(float2& d, double2 v) { d = narrow(v); }
+__device__ __forceinline__ void tput(double2& d, double2 v) { d = v; }
+__device__ __forceinline__ double2 tget(const float2& d) { return widen<double2>(d); }
+__device__ __forceinline__ double2 tget(const double2& d) { return d; }
 
 // hub index of (kz, kx, ky_pos)
 template <int N>
@@ -45,55 +75,71 @@ __device__ __forceinline__ int hidx(int kz, int kx, int kyp) {
   return (kz * LD<N>::NK + kx) * N + kyp;
 }
 
-// The fixed coordinates of a line and the part of the squared sinc argument
-// that they contribute.
+// The fixed coordinates of a line.
 //   x lines (AX 0): lg = kz N + ky_pos, kz <= N/2 (the Hermitian half)
 //   y lines (AX 1): lg = kz (N/2+1) + kx
 //   z lines (AX 2): lg = kx N + ky_pos
 template <int N, int AX>
 struct LineGeo {
-  int lg, kx, kyp, kz, kyn;   // kyn: ky_pos of -ky
-  double s0;
-  __device__ __forceinline__ LineGeo(int tile, int l, const LineTables& T) {
+  int lg, kx, kyp, kz, kyf, kyn;   // kyf: natural ky of ky_pos, kyn: ky_pos of -ky
+  __device__ __forceinline__ LineGeo(int tile, int l) {
     using D = LD<N>;
     lg = tile * kLT + l;
     if (AX == 0) { kyp = lg % N; kz = lg / N; kx = 0; }
     else if (AX == 1) { kx = lg % D::NK; kz = lg / D::NK; kyp = 0; }
     else { kyp = lg % N; kx = lg / N; kz = 0; }
-    const int kyf = fft_freq(N, kyp);
+    kyf = fft_freq(N, kyp);
     kyn = fft_pos(N, (N - kyf) % N);
-    double ha, hb;
-    if (AX == 0) { ha = T.h[kyf]; hb = T.h[kz]; }
-    else if (AX == 1) { ha = T.h[kx]; hb = T.h[kz]; }
-    else { ha = T.h[kx]; hb = T.h[kyf]; }
-    s0 = ha * ha + hb * hb;
   }
-  // k-space correction at frequency f along the line
-  __device__ __forceinline__ double kappa(const LineTables& T, int f) const {
-    const double hf = T.h[f];
-    return sinc_of_sq(s0 + hf * hf);
+  // the part of the squared sinc argument that the fixed coordinates contribute
+  __device__ __forceinline__ double s0(const double* h) const {
+    double ha, hb;
+    if (AX == 0) { ha = h[kyf]; hb = h[kz]; }
+    else if (AX == 1) { ha = h[kx]; hb = h[kz]; }
+    else { ha = h[kx]; hb = h[kyf]; }
+    return ha * ha + hb * hb;
   }
 };
 
-// Sum of nh component spectra at frequency f (natural) / position p along the
-// line. x lines read kx > N/2 as the conjugate at (-kx, -ky, -kz).
+__device__ __forceinline__ double kappa_at(const double* h, double s0, int f) {
+  const double hf = h[f];
+  return sinc_of_sq(s0 + hf * hf);
+}
+
+// Hub index of frequency f (natural) / position p along the line; x lines read
+// kx > N/2 as the conjugate at (-kx, -ky, -kz) (cj set).
+template <int N, int AX>
+__device__ __forceinline__ int hub_addr(const LineGeo<N, AX>& g, int f, int p, bool& cj) {
+  using D = LD<N>;
+  cj = false;
+  if (AX == 0) {
+    if (f <= D::H) return hidx<N>(g.kz, f, g.kyp);
+    cj = true;
+    return hidx<N>((N - g.kz) % N, N - f, g.kyn);
+  }
+  if (AX == 1) return hidx<N>(g.kz, g.kx, p);
+  return hidx<N>(f, g.kx, g.kyp);
+}
+
+// Index into the plane spectrum S[kx][ky_pos] (adjoint source, the same for every kz).
+template <int N, int AX>
+__device__ __forceinline__ int src_addr(const LineGeo<N, AX>& g, int f, int p, bool& cj) {
+  using D = LD<N>;
+  cj = false;
+  if (AX == 0) {
+    if (f <= D::H) return f * N + g.kyp;
+    cj = true;
+    return (N - f) * N + g.kyn;
+  }
+  if (AX == 1) return g.kx * N + p;
+  return g.kx * N + g.kyp;
+}
+
+// Sum of nh component spectra at frequency f / position p along the line.
 template <int N, int AX>
 __device__ __forceinline__ double2 hub_sum(const float2* const* h, int nh, const LineGeo<N, AX>& g, int f, int p) {
-  using D = LD<N>;
-  int idx;
-  bool cj = false;
-  if (AX == 0) {
-    if (f <= D::H) {
-      idx = hidx<N>(g.kz, f, g.kyp);
-    } else {
-      idx = hidx<N>((N - g.kz) % N, N - f, g.kyn);
-      cj = true;
-    }
-  } else if (AX == 1) {
-    idx = hidx<N>(g.kz, g.kx, p);
-  } else {
-    idx = hidx<N>(f, g.kx, g.kyp);
-  }
+  bool cj;
+  const int idx = hub_addr<N, AX>(g, f, p, cj);
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -105,19 +151,6 @@ __device__ __forceinline__ double2 hub_sum(const float2* const* h, int nh, const
   }
   if (cj) s.y = -s.y;
   return s;
-}
-
-// Adjoint source: the plane spectrum S[kx][ky_pos] of c0^2 y^n, the same for every kz.
-template <int N, int AX>
-__device__ __forceinline__ double2 src_val(const float2* S, const LineGeo<N, AX>& g, int f, int p) {
-  using D = LD<N>;
-  if (AX == 0) {
-    if (f <= D::H) return widen<double2>(S[f * N + g.kyp]);
-    const float2 v = S[(N - f) * N + g.kyn];
-    return make_double2(v.x, -v.y);
-  }
-  if (AX == 1) return widen<double2>(S[g.kx * N + p]);
-  return widen<double2>(S[g.kx * N + g.kyp]);
 }
 
 // Store the value of frequency f / position p of the line into a component
@@ -136,6 +169,19 @@ __device__ __forceinline__ void hub_store(float2* out, const LineGeo<N, AX>& g, 
     out[hidx<N>(f, g.kx, g.kyp)] = narrow(v);
   }
 }
+
+// Element (point n1 + M m, line lg) of a [point][line] state as a wave-uniform
+// base per m plus one 32-bit lane offset, so the 16 points of a stage-0
+// butterfly share one address register.
+template <int N>
+struct StateAt {
+  unsigned off;
+  __device__ __forceinline__ StateAt(int n1, int lg) : off((unsigned)(n1 * LD<N>::NL + lg) * 8u) {}
+  template <typename P>
+  __device__ __forceinline__ P* operator()(P* base, int m) const {
+    return reinterpret_cast<P*>(reinterpret_cast<char*>(base + (size_t)(LD<N>::M * m) * LD<N>::NL) + off);
+  }
+};
 
 // Stage-0 twiddles w^(n1 k), k = 1..R-1, from w = tw[n1] by repeated multiplication.
 template <int R, bool INV>
@@ -159,98 +205,162 @@ struct S1Reg {
   double2 v[LD<N>::I1][LD<N>::M];
 };
 
-// stage-1 registers (after an inverse stage-1 DFT) -> T
+// stage-1 values (after an inverse stage-1 DFT) -> T
 template <int N>
-__device__ __forceinline__ void s1_to_T(LineLds<N>& L, S1Reg<N>& r, int i, int l, int mb) {
+__device__ __forceinline__ void s1_to_T(LineLds<N>& L, const double2* v, int l, int mb) {
   using D = LD<N>;
 #pragma unroll
-  for (int n1 = 0; n1 < D::M; ++n1) L.T[(D::M * mb + n1) * kLT + l] = r.v[i][n1];
+  for (int n1 = 0; n1 < D::M; ++n1) tput(L.T[(D::M * mb + n1) * kLT + l], v[n1]);
 }
 
-// T -> stage-1 registers, forward stage-1 DFT
+// T -> stage-1 values, forward stage-1 DFT
 template <int N>
-__device__ __forceinline__ void T_to_s1_fwd(const LineLds<N>& L, S1Reg<N>& r, int i, int l, int mb) {
+__device__ __forceinline__ void T_to_s1_fwd(const LineLds<N>& L, double2* v, int l, int mb) {
   using D = LD<N>;
 #pragma unroll
-  for (int k1 = 0; k1 < D::M; ++k1) r.v[i][k1] = L.T[(D::M * mb + k1) * kLT + l];
-  dft_r<D::M, false>(r.v[i]);
+  for (int k1 = 0; k1 < D::M; ++k1) v[k1] = tget(L.T[(D::M * mb + k1) * kLT + l]);
+  dft_r<D::M, false>(v);
 }
 
 // T -> stage-0 registers, inverse stage 0 (natural points n1 + M m)
 template <int N>
-__device__ __forceinline__ void T_to_s0_inv(const LineLds<N>& L, S0Reg<N>& r, int i, int l, int n1,
-                                            const LineTables& T) {
+__device__ __forceinline__ void T_to_s0_inv(const LineLds<N>& L, double2* a, int l, int n1, const double2* tw) {
   using D = LD<N>;
 #pragma unroll
-  for (int m = 0; m < D::R0; ++m) r.a[i][m] = L.T[(n1 + D::M * m) * kLT + l];
-  if constexpr (D::M > 1) twiddle_pow<D::R0, true>(r.a[i], T.tw[n1]);
-  dft_r<D::R0, true>(r.a[i]);
+  for (int m = 0; m < D::R0; ++m) a[m] = tget(L.T[(n1 + D::M * m) * kLT + l]);
+  if constexpr (D::M > 1) twiddle_pow<D::R0, true>(a, tw[n1]);
+  dft_r<D::R0, true>(a);
 }
 
 // stage-0 registers (natural points) -> forward stage 0 -> T (the slots the
 // same thread read in T_to_s0_inv, so no barrier is needed before it)
 template <int N>
-__device__ __forceinline__ void s0_fwd_to_T(LineLds<N>& L, S0Reg<N>& r, int i, int l, int n1, const LineTables& T) {
+__device__ __forceinline__ void s0_fwd_to_T(LineLds<N>& L, double2* a, int l, int n1, const double2* tw) {
   using D = LD<N>;
-  dft_r<D::R0, false>(r.a[i]);
-  if constexpr (D::M > 1) twiddle_pow<D::R0, false>(r.a[i], T.tw[n1]);
+  dft_r<D::R0, false>(a);
+  if constexpr (D::M > 1) twiddle_pow<D::R0, false>(a, tw[n1]);
 #pragma unroll
-  for (int k = 0; k < D::R0; ++k) L.T[(n1 + D::M * k) * kLT + l] = r.a[i][k];
+  for (int k = 0; k < D::R0; ++k) tput(L.T[(n1 + D::M * k) * kLT + l], a[k]);
 }
 
 enum LineMode { LM_FWD_INIT = 0, LM_FWD_STEP = 1, LM_ADJ_STEP = 2, LM_ADJ_FINAL = 3 };
 
 struct LineStepArgs {
-  const float2* hin[3];   // component spectra read and summed
-  int nh;                 // how many of them (the others are zero)
+  const float2* hin[3];   // component spectra read and summed (the kernel's NH of them)
   double hscale;          // factor of their sum
   const float2* src;      // adjoint: source plane spectrum added to the hub
   float2* hout[3];        // output component spectra
   float2* plane;          // forward step: plane spectrum of the hub read (z lines), or null
-  int first;              // adjoint: states of the previous step are zero
 };
 
-// One tile of lines of axis AX.
-template <int N, int AX, int MODE>
-__device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, const LineScalars& sc,
+// One tile of lines of axis AX. Global loads are issued ahead of their use:
+// all hub loads of a stage-1 item together, each state one phase before its
+// update.
+template <int N, int AX, int MODE, int NH>
+__device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, const LineScalars& sc,
                                           const LineBuffers& B, const LineStepArgs& A, int tile, int tid) {
   using D = LD<N>;
   constexpr int R0 = D::R0, M = D::M;
   constexpr bool ADJ = MODE == LM_ADJ_STEP || MODE == LM_ADJ_FINAL;
+  // NH component spectra are summed (compile time, so the loads carry no
+  // branches); an adjoint step that reads none is the first, with zero states
+  constexpr bool reads = !(ADJ && NH == 0);
+  static_assert(N <= kThreadsL, "one table entry per thread");
   float2* su = B.su[AX];
   float2* sr = B.sr[AX];
-  const float* pa = T.a[AX];
-  const float* pb = T.b[AX];
   const bool want_plane = !ADJ && AX == 2 && A.plane != nullptr;
-  S1Reg<N> s1;
-  S0Reg<N> s0;
-  double2 psum = make_double2(0.0, 0.0);
+  const LTab T{L.h, L.mp, L.mm, L.tw, L.a, L.b};
 
-  // (A) the hub at the line's frequencies, times the first multiplier, inverse stage 1
+  // tables: one entry of each per thread
+  double th = 0.0;
+  double2 tmp = make_double2(0.0, 0.0), tmm = tmp, ttw = tmp;
+  float ta = 0.f, tb = 0.f;
+  if (tid < N) {
+    th = Tg.h[tid];
+    tmp = Tg.mp[tid];
+    tmm = Tg.mm[tid];
+    ttw = Tg.tw[tid];
+    ta = Tg.a[AX][tid];
+    tb = Tg.b[AX][tid];
+  }
+
+  float2 pre1[D::I0][R0], pre2[D::I0][R0];
+  float2* st1 = ADJ ? sr : su;
+  float2* st2 = ADJ ? su : sr;
+
+  if (tid < N) {
+    L.h[tid] = th;
+    L.mp[tid] = tmp;
+    L.mm[tid] = tmm;
+    L.tw[tid] = ttw;
+    L.a[tid] = ta;
+    L.b[tid] = tb;
+  }
+  __syncthreads();
+
+  // (A) per stage-1 item: the hub (and the adjoint source) at its frequencies,
+  // loads issued together; sum, first multiplier, inverse stage 1
+  double2 psum = make_double2(0.0, 0.0);
+  S1Reg<N> keep;   // forward init: the hub values, for the second transform
 #pragma unroll
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l, T);
+      const LineGeo<N, AX> g(tile, l);
+      float2 hv[M][NH > 0 ? NH : 1], sv[M];
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
         const int f = mb + R0 * k1, p = M * mb + k1;
-        double2 P = hub_sum<N, AX>(A.hin, A.nh, g, f, p);
+        bool cj;
+        const int idx = hub_addr<N, AX>(g, f, p, cj);
+#pragma unroll
+        for (int c = 0; c < NH; ++c) hv[k1][c] = A.hin[c][idx];
+        if (ADJ) sv[k1] = A.src[src_addr<N, AX>(g, f, p, cj)];
+      }
+      const double s0 = g.s0(T.h);
+      double2 v[M];
+#pragma unroll
+      for (int k1 = 0; k1 < M; ++k1) {
+        const int f = mb + R0 * k1;
+        double2 P = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NH; ++c) P = cadd(P, widen<double2>(hv[k1][c]));
+        const bool cj = AX == 0 && f > D::H;
+        if (cj) P.y = -P.y;
         P = cscale(P, A.hscale);
-        if (ADJ) P = cadd(P, src_val<N, AX>(A.src, g, f, p));
+        if (ADJ) {
+          double2 S = widen<double2>(sv[k1]);
+          if (cj) S.y = -S.y;
+          P = cadd(P, S);
+        }
         if (want_plane) psum = cadd(psum, P);
-        if (MODE == LM_FWD_STEP) P = cscale(cmul(P, T.mp[f]), g.kappa(T, f) * sc.inv_n);
+        if (MODE == LM_FWD_INIT) keep.v[i][k1] = P;
+        if (MODE == LM_FWD_STEP) P = cscale(cmul(P, T.mp[f]), kappa_at(T.h, s0, f) * sc.inv_n);
         else if (MODE == LM_FWD_INIT) P = cscale(P, sc.inv_n * sc.inv_3c2);
         else P = cscale(P, sc.inv_n);
-        s1.v[i][k1] = P;
+        v[k1] = P;
       }
-      dft_r<M, true>(s1.v[i]);
-      s1_to_T<N>(L, s1, i, l, mb);
+      dft_r<M, true>(v);
+      s1_to_T<N>(L, v, l, mb);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // one item at a time: bounds the live registers
+  }
+  // the state of the first update (forward u, adjoint rho^), in flight across the barrier
+  if (MODE != LM_FWD_INIT && reads) {
+#pragma unroll
+    for (int i = 0; i < D::I0; ++i) {
+      const int b = tid + i * kThreadsL;
+      if (b < D::N0) {
+        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) pre1[i][m] = *at(st1, m);
+      }
     }
   }
   __syncthreads();
 
+  S0Reg<N> s0r;
   if constexpr (MODE == LM_FWD_INIT) {
     // rho = F^-1 P / (3 c0^2), u = dt/(2 rho0) F^-1 [m+ P]
 #pragma unroll
@@ -258,9 +368,9 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
       const int b = tid + i * kThreadsL;
       if (b < D::N0) {
         const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
-        T_to_s0_inv<N>(L, s0, i, l, n1, T);
+        T_to_s0_inv<N>(L, s0r.a[i], l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) sr[(n1 + M * m) * D::NL + lg] = narrow(s0.a[i][m]);
+        for (int m = 0; m < R0; ++m) sr[(n1 + M * m) * D::NL + lg] = narrow(s0r.a[i][m]);
       }
     }
     __syncthreads();
@@ -269,15 +379,16 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
       const int b = tid + i * kThreadsL;
       if (b < D::N1) {
         const int l = b % kLT, mb = b / kLT;
-        const LineGeo<N, AX> g(tile, l, T);
+        const LineGeo<N, AX> g(tile, l);
+        const double s0 = g.s0(T.h);
+        double2 v[M];
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) {
-          const int f = mb + R0 * k1, p = M * mb + k1;
-          const double2 P = cscale(hub_sum<N, AX>(A.hin, A.nh, g, f, p), A.hscale);
-          s1.v[i][k1] = cscale(cmul(P, T.mp[f]), g.kappa(T, f) * sc.inv_n * sc.half_dt_over_rho0);
+          const int f = mb + R0 * k1;
+          v[k1] = cscale(cmul(keep.v[i][k1], T.mp[f]), kappa_at(T.h, s0, f) * sc.inv_n * sc.half_dt_over_rho0);
         }
-        dft_r<M, true>(s1.v[i]);
-        s1_to_T<N>(L, s1, i, l, mb);
+        dft_r<M, true>(v);
+        s1_to_T<N>(L, v, l, mb);
       }
     }
     __syncthreads();
@@ -286,69 +397,77 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
       const int b = tid + i * kThreadsL;
       if (b < D::N0) {
         const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
-        T_to_s0_inv<N>(L, s0, i, l, n1, T);
+        T_to_s0_inv<N>(L, s0r.a[i], l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) su[(n1 + M * m) * D::NL + lg] = narrow(s0.a[i][m]);
+        for (int m = 0; m < R0; ++m) su[(n1 + M * m) * D::NL + lg] = narrow(s0r.a[i][m]);
       }
     }
     return;
   }
 
+  // the state of the second update (forward rho, adjoint v), in flight during (B) and (C)
+  if (MODE != LM_ADJ_FINAL && reads) {
+#pragma unroll
+    for (int i = 0; i < D::I0; ++i) {
+      const int b = tid + i * kThreadsL;
+      if (b < D::N0) {
+        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) pre2[i][m] = *at(st2, m);
+      }
+    }
+  }
+
   // (B) first update in the natural layout, forward stage 0
   //   forward: u <- a (a u - dt/rho0 g), transform u
-  //   adjoint: rho^ <- b^2 rho^ + q, transform b rho^
+  //   adjoint: rho^ <- b^2 rho^ + q, transform b rho^ (final: rho^ / (3 c0^2))
 #pragma unroll
   for (int i = 0; i < D::I0; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N0) {
-      const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
-      T_to_s0_inv<N>(L, s0, i, l, n1, T);
-      if (!ADJ) {
+      const int l = b % kLT, n1 = b / kLT;
+      const StateAt<N> at(n1, tile * kLT + l);
+      double2* a = s0r.a[i];
+      T_to_s0_inv<N>(L, a, l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) {
-          const int x = n1 + M * m, idx = x * D::NL + lg;
-          const double af = pa[x];
-          const double2 uo = widen<double2>(su[idx]);
-          const double2 un = make_double2(af * (af * uo.x - sc.dt_over_rho0 * s0.a[i][m].x),
-                                          af * (af * uo.y - sc.dt_over_rho0 * s0.a[i][m].y));
-          su[idx] = narrow(un);
-          s0.a[i][m] = un;
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < R0; ++m) {
-          const int x = n1 + M * m, idx = x * D::NL + lg;
-          const double bf = pb[x];
-          double2 rh = s0.a[i][m];
-          if (!A.first) {
-            const double2 ro = widen<double2>(sr[idx]);
+      for (int m = 0; m < R0; ++m) {
+        const int x = n1 + M * m;
+        if (!ADJ) {
+          const double af = T.a[x];
+          const double2 uo = widen<double2>(pre1[i][m]);
+          const double2 un = make_double2(af * (af * uo.x - sc.dt_over_rho0 * a[m].x),
+                                          af * (af * uo.y - sc.dt_over_rho0 * a[m].y));
+          *at(su, m) = narrow(un);
+          a[m] = un;
+        } else {
+          const double bf = T.b[x];
+          double2 rh = a[m];
+          if (reads) {
+            const double2 ro = widen<double2>(pre1[i][m]);
             rh = make_double2(bf * bf * ro.x + rh.x, bf * bf * ro.y + rh.y);
           }
           if (MODE == LM_ADJ_STEP) {
-            sr[idx] = narrow(rh);
-            s0.a[i][m] = cscale(rh, bf);
+            *at(sr, m) = narrow(rh);
+            a[m] = cscale(rh, bf);
           } else {
-            s0.a[i][m] = cscale(rh, sc.inv_3c2);
+            a[m] = cscale(rh, sc.inv_3c2);
           }
         }
       }
-      s0_fwd_to_T<N>(L, s0, i, l, n1, T);
+      s0_fwd_to_T<N>(L, a, l, n1, T.tw);
     }
   }
   __syncthreads();
 
   if constexpr (MODE == LM_ADJ_FINAL) {
     // out = F(rho^) / (3 c0^2) - dt/(2 rho0) m- F(v)
+    S1Reg<N> s1;
 #pragma unroll
     for (int i = 0; i < D::I1; ++i) {
       const int b = tid + i * kThreadsL;
-      if (b < D::N1) {
-        const int l = b % kLT, mb = b / kLT;
-        T_to_s1_fwd<N>(L, s1, i, l, mb);
-      }
+      if (b < D::N1) T_to_s1_fwd<N>(L, s1.v[i], b % kLT, b / kLT);
     }
-    if (!A.first) {
-      S1Reg<N> w;
+    if (reads) {
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < D::I0; ++i) {
@@ -356,8 +475,8 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
         if (b < D::N0) {
           const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
 #pragma unroll
-          for (int m = 0; m < R0; ++m) s0.a[i][m] = widen<double2>(su[(n1 + M * m) * D::NL + lg]);
-          s0_fwd_to_T<N>(L, s0, i, l, n1, T);
+          for (int m = 0; m < R0; ++m) s0r.a[i][m] = widen<double2>(su[(n1 + M * m) * D::NL + lg]);
+          s0_fwd_to_T<N>(L, s0r.a[i], l, n1, T.tw);
         }
       }
       __syncthreads();
@@ -366,12 +485,14 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
         const int b = tid + i * kThreadsL;
         if (b < D::N1) {
           const int l = b % kLT, mb = b / kLT;
-          const LineGeo<N, AX> g(tile, l, T);
-          T_to_s1_fwd<N>(L, w, i, l, mb);
+          const LineGeo<N, AX> g(tile, l);
+          const double s0 = g.s0(T.h);
+          double2 w[M];
+          T_to_s1_fwd<N>(L, w, l, mb);
 #pragma unroll
           for (int k1 = 0; k1 < M; ++k1) {
             const int f = mb + R0 * k1;
-            const double2 t = cscale(cmul(w.v[i][k1], T.mm[f]), g.kappa(T, f) * sc.half_dt_over_rho0);
+            const double2 t = cscale(cmul(w[k1], T.mm[f]), kappa_at(T.h, s0, f) * sc.half_dt_over_rho0);
             s1.v[i][k1] = csub(s1.v[i][k1], t);
           }
         }
@@ -382,7 +503,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
       const int b = tid + i * kThreadsL;
       if (b < D::N1) {
         const int l = b % kLT, mb = b / kLT;
-        const LineGeo<N, AX> g(tile, l, T);
+        const LineGeo<N, AX> g(tile, l);
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) hub_store<N, AX>(A.hout[AX], g, mb + R0 * k1, M * mb + k1, s1.v[i][k1]);
       }
@@ -391,20 +512,22 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
   }
 
   // (C) forward stage 1, middle multiplier (forward m-, adjoint m+), inverse stage 1
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l, T);
-      T_to_s1_fwd<N>(L, s1, i, l, mb);
+      const LineGeo<N, AX> g(tile, l);
+      const double s0 = g.s0(T.h);
+      double2 v[M];
+      T_to_s1_fwd<N>(L, v, l, mb);
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
         const int f = mb + R0 * k1;
-        s1.v[i][k1] = cscale(cmul(s1.v[i][k1], ADJ ? T.mp[f] : T.mm[f]), g.kappa(T, f) * sc.inv_n);
+        v[k1] = cscale(cmul(v[k1], ADJ ? T.mp[f] : T.mm[f]), kappa_at(T.h, s0, f) * sc.inv_n);
       }
-      dft_r<M, true>(s1.v[i]);
-      s1_to_T<N>(L, s1, i, l, mb);
+      dft_r<M, true>(v);
+      s1_to_T<N>(L, v, l, mb);
     }
   }
   __syncthreads();
@@ -416,48 +539,48 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
   for (int i = 0; i < D::I0; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N0) {
-      const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
-      T_to_s0_inv<N>(L, s0, i, l, n1, T);
-      if (!ADJ) {
+      const int l = b % kLT, n1 = b / kLT;
+      const StateAt<N> at(n1, tile * kLT + l);
+      double2* a = s0r.a[i];
+      T_to_s0_inv<N>(L, a, l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) {
-          const int x = n1 + M * m, idx = x * D::NL + lg;
-          const double bf = pb[x];
-          const double2 ro = widen<double2>(sr[idx]);
-          const double2 rn = make_double2(bf * (bf * ro.x - sc.dt_rho0 * s0.a[i][m].x),
-                                          bf * (bf * ro.y - sc.dt_rho0 * s0.a[i][m].y));
-          sr[idx] = narrow(rn);
-          s0.a[i][m] = rn;
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < R0; ++m) {
-          const int x = n1 + M * m, idx = x * D::NL + lg;
-          const double af = pa[x];
-          double2 uh = cscale(s0.a[i][m], sc.dt_rho0);
-          if (!A.first) uh = cadd(uh, widen<double2>(su[idx]));
-          su[idx] = narrow(cscale(uh, af * af));
-          s0.a[i][m] = cscale(uh, af);
+      for (int m = 0; m < R0; ++m) {
+        const int x = n1 + M * m;
+        if (!ADJ) {
+          const double bf = T.b[x];
+          const double2 ro = widen<double2>(pre2[i][m]);
+          const double2 rn = make_double2(bf * (bf * ro.x - sc.dt_rho0 * a[m].x),
+                                          bf * (bf * ro.y - sc.dt_rho0 * a[m].y));
+          *at(sr, m) = narrow(rn);
+          a[m] = rn;
+        } else {
+          const double af = T.a[x];
+          double2 uh = cscale(a[m], sc.dt_rho0);
+          if (reads) uh = cadd(uh, widen<double2>(pre2[i][m]));
+          *at(su, m) = narrow(cscale(uh, af * af));
+          a[m] = cscale(uh, af);
         }
       }
-      s0_fwd_to_T<N>(L, s0, i, l, n1, T);
+      s0_fwd_to_T<N>(L, a, l, n1, T.tw);
     }
   }
   __syncthreads();
 
   // (E) forward stage 1 and the output spectrum (adjoint: times m-)
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l, T);
-      T_to_s1_fwd<N>(L, s1, i, l, mb);
+      const LineGeo<N, AX> g(tile, l);
+      const double s0 = g.s0(T.h);
+      double2 v[M];
+      T_to_s1_fwd<N>(L, v, l, mb);
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
         const int f = mb + R0 * k1, p = M * mb + k1;
-        double2 o = s1.v[i][k1];
-        if (ADJ) o = cscale(cmul(o, T.mm[f]), g.kappa(T, f));
+        double2 o = v[k1];
+        if (ADJ) o = cscale(cmul(o, T.mm[f]), kappa_at(T.h, s0, f));
         hub_store<N, AX>(A.hout[AX], g, f, p, o);
       }
     }
@@ -465,24 +588,25 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& T, co
 
   if (want_plane) {   // sum over kz of the hub read: the plane z = 0 of the pressure, / N^3
     __syncthreads();
-    L.T[tid] = psum;
+    tput(L.T[tid], psum);
     __syncthreads();
     if (tid < kLT) {
       double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int j = 0; j < kThreadsL / kLT; ++j) s = cadd(s, L.T[tid + kLT * j]);
+      for (int j = 0; j < kThreadsL / kLT; ++j) s = cadd(s, tget(L.T[tid + kLT * j]));
       A.plane[tile * kLT + tid] = narrow(cscale(s, sc.inv_ntot));
     }
   }
 }
 
-template <int N, int MODE>
-__global__ __launch_bounds__(kThreadsL) void k_line(LineTables T, LineScalars sc, LineBuffers B, LineStepArgs A) {
+template <int N, int MODE, int NH>
+__global__ __launch_bounds__(kThreadsL, MODE == LM_ADJ_FINAL ? 1 : PAT_LINE_WAVES) void k_line(
+    LineTables T, LineScalars sc, LineBuffers B, LineStepArgs A) {
   __shared__ LineLds<N> L;
   const int tile = blockIdx.x, tid = threadIdx.x;
-  if (blockIdx.y == 0) line_tile<N, 0, MODE>(L, T, sc, B, A, tile, tid);
-  else if (blockIdx.y == 1) line_tile<N, 1, MODE>(L, T, sc, B, A, tile, tid);
-  else line_tile<N, 2, MODE>(L, T, sc, B, A, tile, tid);
+  if (blockIdx.y == 0) line_tile<N, 0, MODE, NH>(L, T, sc, B, A, tile, tid);
+  else if (blockIdx.y == 1) line_tile<N, 1, MODE, NH>(L, T, sc, B, A, tile, tid);
+  else line_tile<N, 2, MODE, NH>(L, T, sc, B, A, tile, tid);
 }
 
 // Slab spectrum [z][kx][ky_pos] (z lines: [point][line]) -> z transform ->
@@ -493,16 +617,15 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zfwd(LineTables T, const flo
   using D = LD<N>;
   __shared__ LineLds<N> L;
   const int tile = blockIdx.x, tid = threadIdx.x;
-  S0Reg<N> s0;
-  S1Reg<N> s1;
+  double2 a[D::R0];
 #pragma unroll
   for (int i = 0; i < D::I0; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N0) {
       const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
 #pragma unroll
-      for (int m = 0; m < D::R0; ++m) s0.a[i][m] = widen<double2>(spec[(n1 + D::M * m) * D::NL + lg]);
-      s0_fwd_to_T<N>(L, s0, i, l, n1, T);
+      for (int m = 0; m < D::R0; ++m) a[m] = widen<double2>(spec[(n1 + D::M * m) * D::NL + lg]);
+      s0_fwd_to_T<N>(L, a, l, n1, T.tw);
     }
   }
   __syncthreads();
@@ -511,11 +634,11 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zfwd(LineTables T, const flo
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, 2> g(tile, l, T);
-      T_to_s1_fwd<N>(L, s1, i, l, mb);
+      const LineGeo<N, 2> g(tile, l);
+      double2 v[D::M];
+      T_to_s1_fwd<N>(L, v, l, mb);
 #pragma unroll
-      for (int k1 = 0; k1 < D::M; ++k1)
-        hub_store<N, 2>(hub, g, mb + D::R0 * k1, D::M * mb + k1, cscale(s1.v[i][k1], scale));
+      for (int k1 = 0; k1 < D::M; ++k1) hub_store<N, 2>(hub, g, mb + D::R0 * k1, D::M * mb + k1, cscale(v[k1], scale));
     }
   }
 }
@@ -529,19 +652,18 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zinv(LineTables T, const flo
   __shared__ LineLds<N> L;
   const int tile = blockIdx.x, tid = threadIdx.x;
   const float2* hs[3] = {h0, h1, h2};
-  S0Reg<N> s0;
-  S1Reg<N> s1;
 #pragma unroll
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, 2> g(tile, l, T);
+      const LineGeo<N, 2> g(tile, l);
+      double2 v[D::M];
 #pragma unroll
       for (int k1 = 0; k1 < D::M; ++k1)
-        s1.v[i][k1] = cscale(hub_sum<N, 2>(hs, 3, g, mb + D::R0 * k1, D::M * mb + k1), scale);
-      dft_r<D::M, true>(s1.v[i]);
-      s1_to_T<N>(L, s1, i, l, mb);
+        v[k1] = cscale(hub_sum<N, 2>(hs, 3, g, mb + D::R0 * k1, D::M * mb + k1), scale);
+      dft_r<D::M, true>(v);
+      s1_to_T<N>(L, v, l, mb);
     }
   }
   __syncthreads();
@@ -550,9 +672,10 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zinv(LineTables T, const flo
     const int b = tid + i * kThreadsL;
     if (b < D::N0) {
       const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
-      T_to_s0_inv<N>(L, s0, i, l, n1, T);
+      double2 a[D::R0];
+      T_to_s0_inv<N>(L, a, l, n1, T.tw);
 #pragma unroll
-      for (int m = 0; m < D::R0; ++m) spec[(n1 + D::M * m) * D::NL + lg] = narrow(s0.a[i][m]);
+      for (int m = 0; m < D::R0; ++m) spec[(n1 + D::M * m) * D::NL + lg] = narrow(a[m]);
     }
   }
 }
@@ -590,19 +713,18 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
   k_line_zfwd<N><<<D::NTILE, kThreadsL, 0, st>>>(T, B.spec, B.hub[0][0], 1.0 / sc.c2);
   LineStepArgs A{};
   A.hin[0] = B.hub[0][0];
-  A.nh = 1;
   A.hscale = sc.c2;
-  if (nt > 1) k_line<N, LM_FWD_INIT><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
   for (int n = 0; n + 1 < nt; ++n) {
     const int cur = n & 1;
     for (int c = 0; c < 3; ++c) {
       A.hin[c] = B.hub[cur][c];
       A.hout[c] = B.hub[cur ^ 1][c];
     }
-    A.nh = n == 0 ? 1 : 3;
     A.plane = B.planes + (size_t)n * D::NL;
     timed(kt, K_LINE_FWD, st, [&] {
-      k_line<N, LM_FWD_STEP><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_FWD_STEP, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   const int last = (nt - 1) & 1;
@@ -631,11 +753,10 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
       A.hin[c] = B.hub[cur][c];
       A.hout[c] = B.hub[cur ^ 1][c];
     }
-    A.nh = j == 0 ? 0 : 3;
-    A.first = j == 0;
     A.src = B.planes + (size_t)(n + 1) * D::NL;
     timed(kt, K_LINE_ADJ, st, [&] {
-      k_line<N, LM_ADJ_STEP><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_ADJ_STEP, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   cur = (nt - 1) & 1;
@@ -643,10 +764,9 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
     A.hin[c] = B.hub[cur][c];
     A.hout[c] = B.hub[cur ^ 1][c];
   }
-  A.nh = nt == 1 ? 0 : 3;
-  A.first = nt == 1;
   A.src = B.planes;
-  k_line<N, LM_ADJ_FINAL><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt == 1) k_line<N, LM_ADJ_FINAL, 0><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+  else k_line<N, LM_ADJ_FINAL, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
   k_line_zinv<N><<<D::NTILE, kThreadsL, 0, st>>>(T, B.hub[cur ^ 1][0], B.hub[cur ^ 1][1], B.hub[cur ^ 1][2], B.spec,
                                                  sc.inv_ntot);
   e = hipGetLastError();

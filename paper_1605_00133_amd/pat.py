@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpat.so")
+# the in-tree build; PAT_LIB names another build of the same library
+LIB_PATH = os.environ.get("PAT_LIB") or os.path.join(_PKG, "libpat.so")
 
 PAT_SAMPLE_FULL, PAT_SAMPLE_POINTS, PAT_SAMPLE_HADAMARD = 0, 1, 2
 KIND = {"full": PAT_SAMPLE_FULL, "points": PAT_SAMPLE_POINTS, "hadamard": PAT_SAMPLE_HADAMARD}

@@ -27,6 +27,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=1)
     ap.add_argument("--fft-precision", type=int, choices=[32, 64], default=64)
     ap.add_argument("--sampling", choices=["points", "hadamard"], default="points")
+    ap.add_argument("--scheme", choices=["line", "slab"], default="line")
     args = ap.parse_args()
     import torch
     from paper_1605_00133_amd import pat as P
@@ -45,6 +46,8 @@ def main():
         perm, idx = P.pat_make_shd_pattern(npix, mc, 4)
     plan = P.Plan(P.make_grid(n, n, n, 100e-6, 1500.0, 20e-9, nt, 8), args.sampling, mc, idx, perm)
     plan.set_fft_precision(args.fft_precision)
+    if args.fft_precision == 64:
+        plan.set_scheme(args.scheme)
     p0 = torch.from_numpy(vessel_phantom((n, n, n), 8, 24, 1.0, 4.0, 1).astype(np.float32)).to(dev)
     f = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
     p = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
@@ -52,7 +55,8 @@ def main():
         P.pat_forward(plan, p0, f)
         P.pat_adjoint(plan, f, p)
     torch.cuda.synchronize()
-    print(f"profile_pair: {args.pairs} pair(s) at {n}^3 nt={nt} fft f{args.fft_precision} done", flush=True)
+    print(f"profile_pair: {args.pairs} pair(s) at {n}^3 nt={nt} fft f{args.fft_precision} {args.scheme} done",
+          flush=True)
 
 
 if __name__ == "__main__":

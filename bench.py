@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--n-prox", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scheme", choices=["line", "slab"], default="line",
+                    help="propagator implementation (line needs FP64 butterflies)")
     ap.add_argument("--fft-precision", type=int, choices=[32, 64], default=64,
                     help="arithmetic of the FFT butterflies (storage is FP32 either way)")
     args = ap.parse_args()
@@ -126,6 +128,8 @@ def main():
     grid = P.make_grid(n, n, n, 100e-6, 1500.0, 20e-9, nt, pml)
     plan = P.Plan(grid, args.sampling, mc, idx, perm)
     plan.set_fft_precision(args.fft_precision)
+    if args.fft_precision == 64:
+        plan.set_scheme(args.scheme)
     log(f"plan {n}^3 nt={nt} {args.sampling} mc={mc}: workspace {plan.workspace.numel() / 2**20:.0f} MiB")
 
     p0_h = vessel_phantom((n, n, n), pml, 24, 1.0, 4.0, 1)
@@ -205,6 +209,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "fft_arithmetic": f"f{args.fft_precision}",
+        "scheme": args.scheme if args.fft_precision == 64 else "slab",
         "data": "synthetic (random vessel phantom, seeded mask, 1% Gaussian noise)",
         "config": {"workload": f"{n}^3 grid incl. 8-cell PML, Nt={nt}, {args.sampling} sampling mc={mc}, "
                                f"one TV FISTA iteration per step ({args.n_prox} PDHG, restart on) inside TV+Br",

@@ -405,19 +405,6 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
     return;
   }
 
-  // the state of the second update (forward rho, adjoint v), in flight during (B) and (C)
-  if (MODE != LM_ADJ_FINAL && reads) {
-#pragma unroll
-    for (int i = 0; i < D::I0; ++i) {
-      const int b = tid + i * kThreadsL;
-      if (b < D::N0) {
-        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) pre2[i][m] = *at(st2, m);
-      }
-    }
-  }
-
   // (B) first update in the natural layout, forward stage 0
   //   forward: u <- a (a u - dt/rho0 g), transform u
   //   adjoint: rho^ <- b^2 rho^ + q, transform b rho^ (final: rho^ / (3 c0^2))
@@ -455,6 +442,18 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         }
       }
       s0_fwd_to_T<N>(L, a, l, n1, T.tw);
+    }
+  }
+  // the state of the second update (forward rho, adjoint v), in flight during (C)
+  if (MODE != LM_ADJ_FINAL && reads) {
+#pragma unroll
+    for (int i = 0; i < D::I0; ++i) {
+      const int b = tid + i * kThreadsL;
+      if (b < D::N0) {
+        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
+#pragma unroll
+        for (int m = 0; m < R0; ++m) pre2[i][m] = *at(st2, m);
+      }
     }
   }
   __syncthreads();

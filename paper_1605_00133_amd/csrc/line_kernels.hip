@@ -602,9 +602,12 @@ template <int N, int MODE, int NH>
 __global__ __launch_bounds__(kThreadsL, MODE == LM_ADJ_FINAL ? 1 : PAT_LINE_WAVES) void k_line(
     LineTables T, LineScalars sc, LineBuffers B, LineStepArgs A) {
   __shared__ LineLds<N> L;
-  const int tile = blockIdx.x, tid = threadIdx.x;
-  if (blockIdx.y == 0) line_tile<N, 0, MODE, NH>(L, T, sc, B, A, tile, tid);
-  else if (blockIdx.y == 1) line_tile<N, 1, MODE, NH>(L, T, sc, B, A, tile, tid);
+  const int tid = threadIdx.x;
+  // the three axes interleaved in dispatch order: the shorter z tiles mix into
+  // the first round of blocks instead of forming the second alone
+  const int ax = blockIdx.x % 3, tile = blockIdx.x / 3;
+  if (ax == 0) line_tile<N, 0, MODE, NH>(L, T, sc, B, A, tile, tid);
+  else if (ax == 1) line_tile<N, 1, MODE, NH>(L, T, sc, B, A, tile, tid);
   else line_tile<N, 2, MODE, NH>(L, T, sc, B, A, tile, tid);
 }
 
@@ -713,7 +716,7 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
   LineStepArgs A{};
   A.hin[0] = B.hub[0][0];
   A.hscale = sc.c2;
-  if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
   for (int n = 0; n + 1 < nt; ++n) {
     const int cur = n & 1;
     for (int c = 0; c < 3; ++c) {
@@ -722,8 +725,8 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
     }
     A.plane = B.planes + (size_t)n * D::NL;
     timed(kt, K_LINE_FWD, st, [&] {
-      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_FWD_STEP, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_FWD_STEP, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   const int last = (nt - 1) & 1;
@@ -754,8 +757,8 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
     }
     A.src = B.planes + (size_t)(n + 1) * D::NL;
     timed(kt, K_LINE_ADJ, st, [&] {
-      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_ADJ_STEP, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_ADJ_STEP, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   cur = (nt - 1) & 1;
@@ -764,8 +767,8 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
     A.hout[c] = B.hub[cur ^ 1][c];
   }
   A.src = B.planes;
-  if (nt == 1) k_line<N, LM_ADJ_FINAL, 0><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
-  else k_line<N, LM_ADJ_FINAL, 3><<<dim3(D::NTILE, 3), kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt == 1) k_line<N, LM_ADJ_FINAL, 0><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+  else k_line<N, LM_ADJ_FINAL, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
   k_line_zinv<N><<<D::NTILE, kThreadsL, 0, st>>>(T, B.hub[cur ^ 1][0], B.hub[cur ^ 1][1], B.hub[cur ^ 1][2], B.spec,
                                                  sc.inv_ntot);
   e = hipGetLastError();

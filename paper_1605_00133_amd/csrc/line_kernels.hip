@@ -6,8 +6,10 @@
 // 1D transform of length N = R0 M is the two-stage split of fft_radix.hpp; a
 // thread owns one stage-0 butterfly (R0 values at points n1 + M m of one line)
 // or two stage-1 butterflies (M values at positions M mb + k1, frequency
-// mb + R0 k1), with all values FP64 in registers, and the tile T in LDS is the
-// exchange between the stages ([point][line], 16 lines per row). The time step
+// mb + R0 k1), with all arithmetic FP64 in registers, and the tile T in LDS is
+// the exchange between the stages ([point][line], 16 lines per row), stored
+// as FP32 pairs by default (the rounding is of the same size as that of the
+// FP32 states in HBM; FP64 storage doubles the LDS and costs occupancy). The time step
 // of a component is inverse - update - forward - multiply - inverse - update -
 // forward: four transforms and four LDS crossings; the updates run in the
 // stage-0 layout, where a thread holds natural points, and the multipliers in
@@ -36,12 +38,15 @@ struct LD {
   static_assert(N % kLT == 0 && NL % kLT == 0, "a tile is 16 lines");
 };
 
+// PAT_LINE_LDS_F32: tile stored as FP32 (1) or FP64 (0) pairs.
+// PAT_LINE_WAVES: minimum waves per SIMD asked of the register allocator (the
+// step kernels need about 136 VGPRs, which gives three).
 #ifndef PAT_LINE_LDS_F32
-#define PAT_LINE_LDS_F32 0
+#define PAT_LINE_LDS_F32 1
 #endif
 constexpr bool kTF32 = PAT_LINE_LDS_F32 != 0;
 #ifndef PAT_LINE_WAVES
-#define PAT_LINE_WAVES 2
+#define PAT_LINE_WAVES 3
 #endif
 using TStore = std::conditional_t<kTF32, float2, double2>;
 
@@ -191,6 +196,8 @@ __device__ __forceinline__ void twiddle_pow(double2* a, double2 w) {
   for (int k = 1; k < R; ++k) {
     a[k] = INV ? cmulconj(a[k], wk) : cmul(a[k], wk);
     if (k + 1 < R) wk = cmul(wk, w);
+    // in order: otherwise all R - 1 powers are formed first and held in registers
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -253,9 +260,9 @@ struct LineStepArgs {
   float2* plane;          // forward step: plane spectrum of the hub read (z lines), or null
 };
 
-// One tile of lines of axis AX. Global loads are issued ahead of their use:
-// all hub loads of a stage-1 item together, each state one phase before its
-// update.
+// One tile of lines of axis AX. The hub loads of a stage-1 item are issued
+// together; the states are read where they are updated (a load issued a phase
+// earlier costs more in registers, and occupancy, than it hides).
 template <int N, int AX, int MODE, int NH>
 __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, const LineScalars& sc,
                                           const LineBuffers& B, const LineStepArgs& A, int tile, int tid) {
@@ -283,10 +290,6 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
     ta = Tg.a[AX][tid];
     tb = Tg.b[AX][tid];
   }
-
-  float2 pre1[D::I0][R0], pre2[D::I0][R0];
-  float2* st1 = ADJ ? sr : su;
-  float2* st2 = ADJ ? su : sr;
 
   if (tid < N) {
     L.h[tid] = th;
@@ -345,18 +348,6 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
       s1_to_T<N>(L, v, l, mb);
     }
     __builtin_amdgcn_sched_barrier(0);   // one item at a time: bounds the live registers
-  }
-  // the state of the first update (forward u, adjoint rho^), in flight across the barrier
-  if (MODE != LM_FWD_INIT && reads) {
-#pragma unroll
-    for (int i = 0; i < D::I0; ++i) {
-      const int b = tid + i * kThreadsL;
-      if (b < D::N0) {
-        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) pre1[i][m] = *at(st1, m);
-      }
-    }
   }
   __syncthreads();
 
@@ -421,7 +412,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         const int x = n1 + M * m;
         if (!ADJ) {
           const double af = T.a[x];
-          const double2 uo = widen<double2>(pre1[i][m]);
+          const double2 uo = widen<double2>(*at(su, m));
           const double2 un = make_double2(af * (af * uo.x - sc.dt_over_rho0 * a[m].x),
                                           af * (af * uo.y - sc.dt_over_rho0 * a[m].y));
           *at(su, m) = narrow(un);
@@ -430,7 +421,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
           const double bf = T.b[x];
           double2 rh = a[m];
           if (reads) {
-            const double2 ro = widen<double2>(pre1[i][m]);
+            const double2 ro = widen<double2>(*at(sr, m));
             rh = make_double2(bf * bf * ro.x + rh.x, bf * bf * ro.y + rh.y);
           }
           if (MODE == LM_ADJ_STEP) {
@@ -442,18 +433,6 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         }
       }
       s0_fwd_to_T<N>(L, a, l, n1, T.tw);
-    }
-  }
-  // the state of the second update (forward rho, adjoint v), in flight during (C)
-  if (MODE != LM_ADJ_FINAL && reads) {
-#pragma unroll
-    for (int i = 0; i < D::I0; ++i) {
-      const int b = tid + i * kThreadsL;
-      if (b < D::N0) {
-        const StateAt<N> at(b / kLT, tile * kLT + b % kLT);
-#pragma unroll
-        for (int m = 0; m < R0; ++m) pre2[i][m] = *at(st2, m);
-      }
     }
   }
   __syncthreads();
@@ -547,7 +526,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         const int x = n1 + M * m;
         if (!ADJ) {
           const double bf = T.b[x];
-          const double2 ro = widen<double2>(pre2[i][m]);
+          const double2 ro = widen<double2>(*at(sr, m));
           const double2 rn = make_double2(bf * (bf * ro.x - sc.dt_rho0 * a[m].x),
                                           bf * (bf * ro.y - sc.dt_rho0 * a[m].y));
           *at(sr, m) = narrow(rn);
@@ -555,7 +534,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         } else {
           const double af = T.a[x];
           double2 uh = cscale(a[m], sc.dt_rho0);
-          if (reads) uh = cadd(uh, widen<double2>(pre2[i][m]));
+          if (reads) uh = cadd(uh, widen<double2>(*at(su, m)));
           *at(su, m) = narrow(cscale(uh, af * af));
           a[m] = cscale(uh, af);
         }

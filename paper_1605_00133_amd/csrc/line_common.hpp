@@ -13,13 +13,12 @@
 // components and summed from their three outputs. The adjoint runs the
 // transposed recurrence line by line in the same way.
 //
-// Layouts (N = grid edge, H = N/2, NK = H + 1, NL = NK N lines per axis):
+// Layouts (N = grid edge, H = N/2):
 //   hub spectra      [kz][kx <= H][ky_pos]         kz natural, ky_pos digit-reversed
-//   x state          [x][kz <= H][ky_pos]           (Hermitian half in kz)
-//   y state          [y][kz][kx <= H]
-//   z state          [z][kx <= H][ky_pos]
-// so every state is [point][line] with NL lines, and a tile of 16 consecutive
-// lines reads 128 contiguous bytes per point.
+//   states           [point along the axis][slot], N^2/2 slots per axis: one
+//                    line of each conjugate pair (-P, -Q) ~ (P, Q) of the field,
+//                    the four real lines two to a slot (line_kernels.hip, LineGeo)
+// so a tile of 16 consecutive slots reads 128 contiguous bytes per point.
 #pragma once
 
 #include "wave_common.hpp"
@@ -32,6 +31,7 @@ struct LineTables {
   const double2* mm;   // i k exp(-i k dx/2)
   const double* h;     // (c0 dt / 2) k
   const double2* tw;   // exp(-2 pi i j / n), j < n
+  const double* kr;    // sinc(c0 dt |k| / 2) on the real lines: kr[c n + k], |k_perp|^2 = c (pi/dx)^2, c < 3
   const float* a[3];   // PML factor at staggered points i + 1/2, axis x, y, z
   const float* b[3];   // PML factor at collocated points i
 };

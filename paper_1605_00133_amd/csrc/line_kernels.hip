@@ -14,8 +14,9 @@
 // forward: four transforms and four LDS crossings; the updates run in the
 // stage-0 layout, where a thread holds natural points, and the multipliers in
 // the stage-1 layout, where it holds frequencies. HBM traffic per component and
-// step: the hub (three component spectra, summed in FP64), both states in and
-// out, and the output spectrum, each 8 (N/2+1) N^2 bytes.
+// step: its lines of the three component spectra of the hub (summed in FP64),
+// both states in and out (each N^3/2 complex values), and its output spectrum
+// (8 (N/2+1) N^2 bytes, conjugate partners included).
 #include <type_traits>
 
 #include "fft_radix.hpp"
@@ -27,15 +28,40 @@ namespace pat {
 constexpr int kLT = 16;          // lines per tile
 constexpr int kThreadsL = 128;   // threads per tile block
 
+// First position of a run of N/2 - 1 consecutive positions (order of the
+// forward transform) that holds one frequency of every pair (q, -q) with
+// q != 0, N/2; -1 if there is none.
+__host__ __device__ constexpr int kept_run_start(int n) {
+  for (int ks = 0; ks + n / 2 - 1 <= n; ++ks) {
+    bool ok = true;
+    for (int i = 0; i < n / 2 - 1 && ok; ++i) {
+      const int q = fft_freq(n, ks + i);
+      if (q == 0 || q == n / 2) ok = false;
+      for (int j = 0; j < i && ok; ++j)
+        if (fft_freq(n, ks + j) == (n - q) % n) ok = false;
+    }
+    if (ok) return ks;
+  }
+  return -1;
+}
+
 template <int N>
 struct LD {
   static constexpr int H = N / 2, NK = H + 1;
   static constexpr int R0 = fft_radix(N, 0), M = N / R0;
-  static constexpr int NL = NK * N;                                // lines per axis
-  static constexpr int NTILE = NL / kLT;
+  static constexpr int NL = NK * N;          // z lines (kx <= N/2, ky) of the z transform kernels
+  static constexpr int NTILE = NL / kLT;     // their tiles
+  // Line slots of a step (per axis): the planes P = 1..N/2-1 of the half
+  // coordinate in full, the two self-conjugate planes P = 0, N/2 by half (the
+  // other half is conjugate), and their four real lines in pairs: N^2/2 slots.
+  static constexpr int NS = N * N / 2;
+  static constexpr int NREG = (H - 1) * N;   // slots of the regular planes
+  static constexpr int NT = NS / kLT;        // step tiles per axis
+  static constexpr int KS = kept_run_start(N);
   static constexpr int N0 = kLT * M, I0 = cdiv(N0, kThreadsL);    // stage-0 butterflies per tile
   static constexpr int N1 = kLT * R0, I1 = cdiv(N1, kThreadsL);   // stage-1 butterflies per tile
-  static_assert(N % kLT == 0 && NL % kLT == 0, "a tile is 16 lines");
+  static_assert(N % kLT == 0 && NL % kLT == 0 && NS % kLT == 0, "a tile is 16 lines");
+  static_assert(KS >= 0, "a contiguous run of kept positions");
 };
 
 // PAT_LINE_LDS_F32: tile stored as FP32 (1) or FP64 (0) pairs.
@@ -67,6 +93,7 @@ struct LineLds {
   double h[N];
   double2 mp[N], mm[N], tw[N];
   float a[N], b[N];
+  float2 X[2][N];      // spectra of the two packed slots (last tile), natural frequency order
 };
 
 __device__ __forceinline__ void tput(float2& d, double2 v) { d = narrow(v); }
@@ -80,22 +107,62 @@ __device__ __forceinline__ int hidx(int kz, int kx, int kyp) {
   return (kz * LD<N>::NK + kx) * N + kyp;
 }
 
-// The fixed coordinates of a line.
-//   x lines (AX 0): lg = kz N + ky_pos, kz <= N/2 (the Hermitian half)
-//   y lines (AX 1): lg = kz (N/2+1) + kx
-//   z lines (AX 2): lg = kx N + ky_pos
+// The fixed coordinates of the line in state slot lg. Each axis has a half
+// coordinate P <= N/2 (x lines: kz; y and z lines: kx) and a full one Q (x and
+// z lines: ky_pos; y lines: kz).
+//   regular slots (P = 1..N/2-1): x, z: lg = (P-1) N + ky_pos; y: lg = kz (N/2-1) + P-1
+//   P = 0 and P = N/2: only one line of each conjugate pair (Q, -Q), Q in the run
+//     KS.. of positions (x, z) or kz = 1..N/2-1 (y); the line also writes the
+//     outputs of its partner (kind 1)
+//   last two slots: the real lines (P, 0) and (P, N/2) of P = 0 and P = N/2,
+//     packed as line + i * second line (kind 2)
+// The x lines with 0 < kz < N/2 own the conjugates of their kx >= N/2 outputs too.
 template <int N, int AX>
 struct LineGeo {
   int lg, kx, kyp, kz, kyf, kyn;   // kyf: natural ky of ky_pos, kyn: ky_pos of -ky
-  __device__ __forceinline__ LineGeo(int tile, int l) {
-    using D = LD<N>;
-    lg = tile * kLT + l;
-    if (AX == 0) { kyp = lg % N; kz = lg / N; kx = 0; }
-    else if (AX == 1) { kx = lg % D::NK; kz = lg / D::NK; kyp = 0; }
-    else { kyp = lg % N; kx = lg / N; kz = 0; }
+  int kind;                        // 0 regular, 1 one of a conjugate pair, 2 packed real pair
+  __device__ __forceinline__ void set(int P, int Q) {
+    if (AX == 0) { kz = P; kyp = Q; kx = 0; }
+    else if (AX == 1) { kx = P; kz = Q; kyp = 0; }
+    else { kx = P; kyp = Q; kz = 0; }
     kyf = fft_freq(N, kyp);
     kyn = fft_pos(N, (N - kyf) % N);
   }
+  __device__ __forceinline__ explicit LineGeo(int slot) {
+    using D = LD<N>;
+    lg = slot;
+    int P, Q;
+    if (slot < D::NREG) {
+      kind = 0;
+      if (AX == 1) { P = 1 + slot % (D::H - 1); Q = slot / (D::H - 1); }
+      else { P = 1 + slot / N; Q = slot % N; }
+    } else if (slot < D::NS - 2) {
+      kind = 1;
+      const int j = slot - D::NREG, i = j % (D::H - 1);
+      P = j < D::H - 1 ? 0 : D::H;
+      Q = AX == 1 ? 1 + i : D::KS + i;
+    } else {
+      kind = 2;
+      P = slot == D::NS - 2 ? 0 : D::H;
+      Q = 0;
+    }
+    set(P, Q);
+  }
+  // a z line of the z transform kernels: lg = kx N + ky_pos
+  __device__ __forceinline__ static LineGeo zline(int lg) {
+    LineGeo g;
+    g.lg = lg;
+    g.kind = 0;
+    g.set(lg / N, lg % N);
+    return g;
+  }
+  // the second line of a packed slot: the same P, natural Q = N/2
+  __device__ __forceinline__ LineGeo second() const {
+    LineGeo g = *this;
+    g.set(AX == 0 ? kz : kx, AX == 1 ? N / 2 : fft_pos(N, N / 2));
+    return g;
+  }
+  LineGeo() = default;
   // the part of the squared sinc argument that the fixed coordinates contribute
   __device__ __forceinline__ double s0(const double* h) const {
     double ha, hb;
@@ -159,19 +226,23 @@ __device__ __forceinline__ double2 hub_sum(const float2* const* h, int nh, const
 }
 
 // Store the value of frequency f / position p of the line into a component
-// spectrum. x lines with 0 < kz < N/2 also write the conjugate at
-// (-kx, -ky, -kz) for kx = 0 or kx >= N/2, the half of the spectrum no x line owns.
+// spectrum. The partner line (-Q at -P) of an x line that is not real owns no
+// slot: its outputs are the conjugates at (-kx, -ky, -kz), written for kx = 0
+// or kx >= N/2 (the x lines hold kx <= N/2). y and z lines of kind 1 write
+// their partner's line, the conjugate at (-ky or -kz reversed) too.
 template <int N, int AX>
 __device__ __forceinline__ void hub_store(float2* out, const LineGeo<N, AX>& g, int f, int p, double2 v) {
   using D = LD<N>;
+  const float2 vc = make_float2((float)v.x, (float)-v.y);
   if (AX == 0) {
     if (f <= D::H) out[hidx<N>(g.kz, f, g.kyp)] = narrow(v);
-    if (g.kz >= 1 && g.kz < D::H && (f == 0 || f >= D::H))
-      out[hidx<N>(N - g.kz, (N - f) % N, g.kyn)] = make_float2((float)v.x, (float)-v.y);
+    if (g.kind != 2 && (f == 0 || f >= D::H)) out[hidx<N>((N - g.kz) % N, (N - f) % N, g.kyn)] = vc;
   } else if (AX == 1) {
     out[hidx<N>(g.kz, g.kx, p)] = narrow(v);
+    if (g.kind == 1) out[hidx<N>((N - g.kz) % N, g.kx, fft_pos(N, (N - f) % N))] = vc;
   } else {
     out[hidx<N>(f, g.kx, g.kyp)] = narrow(v);
+    if (g.kind == 1) out[hidx<N>((N - f) % N, g.kx, g.kyn)] = vc;
   }
 }
 
@@ -181,10 +252,10 @@ __device__ __forceinline__ void hub_store(float2* out, const LineGeo<N, AX>& g, 
 template <int N>
 struct StateAt {
   unsigned off;
-  __device__ __forceinline__ StateAt(int n1, int lg) : off((unsigned)(n1 * LD<N>::NL + lg) * 8u) {}
+  __device__ __forceinline__ StateAt(int n1, int lg) : off((unsigned)(n1 * LD<N>::NS + lg) * 8u) {}
   template <typename P>
   __device__ __forceinline__ P* operator()(P* base, int m) const {
-    return reinterpret_cast<P*>(reinterpret_cast<char*>(base + (size_t)(LD<N>::M * m) * LD<N>::NL) + off);
+    return reinterpret_cast<P*>(reinterpret_cast<char*>(base + (size_t)(LD<N>::M * m) * LD<N>::NS) + off);
   }
 };
 
@@ -250,6 +321,30 @@ __device__ __forceinline__ void s0_fwd_to_T(LineLds<N>& L, double2* a, int l, in
   for (int k = 0; k < D::R0; ++k) tput(L.T[(n1 + D::M * k) * kLT + l], a[k]);
 }
 
+// Packed real pairs (last tile, lines 14 and 15): the slot holds z = r1 + i r2
+// with r1, r2 real along the line, so its spectrum Z splits into the Hermitian
+// spectra Z1 = (Z(f) + conj Z(-f)) / 2 and Z2 = (Z(f) - conj Z(-f)) / (2i).
+// packed_spectra writes Z of both slots, from T after a stage-0 pass, to X in
+// natural order (threads 0..2 R0-1, one stage-1 block each); every thread can
+// then split any frequency.
+template <int N>
+__device__ __forceinline__ void packed_spectra(LineLds<N>& L, int tid) {
+  using D = LD<N>;
+  if (tid < 2 * D::R0) {
+    const int r = tid / D::R0, mb = tid % D::R0;
+    double2 v[D::M];
+    T_to_s1_fwd<N>(L, v, kLT - 2 + r, mb);
+#pragma unroll
+    for (int k1 = 0; k1 < D::M; ++k1) L.X[r][mb + D::R0 * k1] = narrow(v[k1]);
+  }
+}
+template <int N>
+__device__ __forceinline__ void packed_split(const LineLds<N>& L, int r, int f, double2& z1, double2& z2) {
+  const double2 z = widen<double2>(L.X[r][f]), zm = widen<double2>(L.X[r][(N - f) % N]);
+  z1 = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+  z2 = make_double2(0.5 * (z.y + zm.y), 0.5 * (zm.x - z.x));
+}
+
 enum LineMode { LM_FWD_INIT = 0, LM_FWD_STEP = 1, LM_ADJ_STEP = 2, LM_ADJ_FINAL = 3 };
 
 struct LineStepArgs {
@@ -259,6 +354,124 @@ struct LineStepArgs {
   float2* hout[3];        // output component spectra
   float2* plane;          // forward step: plane spectrum of the hub read (z lines), or null
 };
+
+// The two packed real pairs of the last tile (lines 14 and 15), handled apart
+// from the item loops (which skip them) by threads 0..2 R0-1, one pair r and
+// stage-1 block mb each, in code that stays small: the sinc on a real line is
+// read from the table kr (kr_line gives its row), not evaluated.
+//
+// Pair r holds the lines (P, 0) and (P, N/2), P = r N/2; row of (P, Q): (P != 0) + (Q != 0).
+__device__ __forceinline__ int kr_row(int r, int w) { return r + w; }
+
+// packed_a: phase A of both lines, z = term(line 1) + i term(line 2), inverse
+// stage 1 into T. kind 0: forward step (m+ sinc P / N), 1: forward init
+// (P / (3 c0^2 N)), 2: the init's second transform (m+ sinc P dt/(2 rho0 N)),
+// 3: adjoint (P / N, P including the source). ps1, ps2: the thread's parts of
+// the plane sums of the two lines (z lines).
+template <int N, int AX, int NH>
+__device__ __forceinline__ void packed_a(LineLds<N>& L, const double* kr, const LineStepArgs& A, double scale,
+                                         int kind, int tid, double2& ps1, double2& ps2) {
+  using D = LD<N>;
+  if (tid < 2 * D::R0) {
+    const int r = tid / D::R0, mb = tid % D::R0;
+    const LineGeo<N, AX> g1(D::NS - 2 + r);
+    double2 v[D::M];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const LineGeo<N, AX> g = w == 0 ? g1 : g1.second();
+      const double* kap = kr + kr_row(r, w) * N;
+      double2 ps = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k1 = 0; k1 < D::M; ++k1) {
+        const int f = mb + D::R0 * k1, p = D::M * mb + k1;
+        bool cj;
+        const int idx = hub_addr<N, AX>(g, f, p, cj);
+        double2 P = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NH; ++c) P = cadd(P, widen<double2>(A.hin[c][idx]));
+        if (cj) P.y = -P.y;
+        P = cscale(P, A.hscale);
+        if (kind == 3) {
+          double2 S = widen<double2>(A.src[src_addr<N, AX>(g, f, p, cj)]);
+          if (cj) S.y = -S.y;
+          P = cadd(P, S);
+        }
+        ps = cadd(ps, P);
+        const double2 t = (kind == 0 || kind == 2) ? cscale(cmul(P, L.mp[f]), kap[f] * scale) : cscale(P, scale);
+        v[k1] = w == 0 ? t : cadd(v[k1], mul_mi<true>(t));
+      }
+      if (w == 0) ps1 = ps;
+      else ps2 = ps;
+    }
+    dft_r<D::M, true>(v);
+    s1_to_T<N>(L, v, kLT - 2 + r, mb);
+  }
+}
+
+// packed_c: phase C of both lines (T holds the stage-0 output of phase B):
+// split the spectrum, each line times its own sinc, times m (m- forward, m+
+// adjoint) / N, inverse stage 1 into T. Every thread of the block calls it.
+template <int N>
+__device__ __forceinline__ void packed_c(LineLds<N>& L, const double* kr, bool adj, double inv_n, int tid) {
+  using D = LD<N>;
+  // the sinc values first: their loads are in flight across the exchange
+  const int r = tid / D::R0 % 2, mb = tid % D::R0;
+  double ka[D::M], kb[D::M];
+#pragma unroll
+  for (int k1 = 0; k1 < D::M; ++k1) {
+    ka[k1] = kr[kr_row(r, 0) * N + mb + D::R0 * k1];
+    kb[k1] = kr[kr_row(r, 1) * N + mb + D::R0 * k1];
+  }
+  packed_spectra<N>(L, tid);
+  __syncthreads();
+  if (tid < 2 * D::R0) {
+    double2 v[D::M];
+#pragma unroll
+    for (int k1 = 0; k1 < D::M; ++k1) {
+      const int f = mb + D::R0 * k1;
+      double2 z1, z2;
+      packed_split<N>(L, r, f, z1, z2);
+      const double2 z = cadd(cscale(z1, ka[k1]), mul_mi<true>(cscale(z2, kb[k1])));
+      v[k1] = cscale(cmul(z, adj ? L.mp[f] : L.mm[f]), inv_n);
+    }
+    dft_r<D::M, true>(v);
+    s1_to_T<N>(L, v, kLT - 2 + r, mb);
+  }
+}
+
+// packed_e: the output spectra of both lines (adjoint: each times m- and its
+// sinc). Every thread of the block calls it.
+template <int N, int AX>
+__device__ __forceinline__ void packed_e(LineLds<N>& L, const double* kr, bool adj, float2* out, int tid) {
+  using D = LD<N>;
+  const int r = tid / D::R0 % 2, mb = tid % D::R0;
+  double ka[D::M], kb[D::M];
+  if (adj) {   // the sinc values first: their loads are in flight across the exchange
+#pragma unroll
+    for (int k1 = 0; k1 < D::M; ++k1) {
+      ka[k1] = kr[kr_row(r, 0) * N + mb + D::R0 * k1];
+      kb[k1] = kr[kr_row(r, 1) * N + mb + D::R0 * k1];
+    }
+  }
+  packed_spectra<N>(L, tid);
+  __syncthreads();
+  if (tid < 2 * D::R0) {
+    const LineGeo<N, AX> g(D::NS - 2 + r);
+    const LineGeo<N, AX> g2 = g.second();
+#pragma unroll
+    for (int k1 = 0; k1 < D::M; ++k1) {
+      const int f = mb + D::R0 * k1, p = D::M * mb + k1;
+      double2 z1, z2;
+      packed_split<N>(L, r, f, z1, z2);
+      if (adj) {
+        z1 = cscale(cmul(z1, L.mm[f]), ka[k1]);
+        z2 = cscale(cmul(z2, L.mm[f]), kb[k1]);
+      }
+      hub_store<N, AX>(out, g, f, p, z1);
+      hub_store<N, AX>(out, g2, f, p, z2);
+    }
+  }
+}
 
 // One tile of lines of axis AX. The hub loads of a stage-1 item are issued
 // together; the states are read where they are updated (a load issued a phase
@@ -277,6 +490,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
   float2* sr = B.sr[AX];
   const bool want_plane = !ADJ && AX == 2 && A.plane != nullptr;
   const LTab T{L.h, L.mp, L.mm, L.tw, L.a, L.b};
+  const bool packed_tile = tile == D::NT - 1;   // holds the two packed real pairs
 
   // tables: one entry of each per thread
   double th = 0.0;
@@ -303,14 +517,14 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
 
   // (A) per stage-1 item: the hub (and the adjoint source) at its frequencies,
   // loads issued together; sum, first multiplier, inverse stage 1
-  double2 psum = make_double2(0.0, 0.0);
-  S1Reg<N> keep;   // forward init: the hub values, for the second transform
+  double2 psum = make_double2(0.0, 0.0), ps1 = psum, ps2 = psum;   // plane sums (ps1, ps2: packed pairs)
+  S1Reg<N> keep;   // forward init: kappa times the hub values, for the second transform
 #pragma unroll
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
-    if (b < D::N1) {
-      const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l);
+    const int l = b % kLT, mb = b / kLT;
+    if (b < D::N1 && !(packed_tile && l >= kLT - 2)) {
+      const LineGeo<N, AX> g(tile * kLT + l);
       float2 hv[M][NH > 0 ? NH : 1], sv[M];
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
@@ -338,7 +552,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
           P = cadd(P, S);
         }
         if (want_plane) psum = cadd(psum, P);
-        if (MODE == LM_FWD_INIT) keep.v[i][k1] = P;
+        if (MODE == LM_FWD_INIT) keep.v[i][k1] = cscale(P, kappa_at(T.h, s0, f));
         if (MODE == LM_FWD_STEP) P = cscale(cmul(P, T.mp[f]), kappa_at(T.h, s0, f) * sc.inv_n);
         else if (MODE == LM_FWD_INIT) P = cscale(P, sc.inv_n * sc.inv_3c2);
         else P = cscale(P, sc.inv_n);
@@ -348,6 +562,11 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
       s1_to_T<N>(L, v, l, mb);
     }
     __builtin_amdgcn_sched_barrier(0);   // one item at a time: bounds the live registers
+  }
+  if (__builtin_expect(packed_tile, 0)) {
+    const int kind = MODE == LM_FWD_STEP ? 0 : MODE == LM_FWD_INIT ? 1 : 3;
+    const double scale = MODE == LM_FWD_INIT ? sc.inv_n * sc.inv_3c2 : sc.inv_n;
+    packed_a<N, AX, NH>(L, Tg.kr, A, scale, kind, tid, ps1, ps2);
   }
   __syncthreads();
 
@@ -361,27 +580,24 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
         T_to_s0_inv<N>(L, s0r.a[i], l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) sr[(n1 + M * m) * D::NL + lg] = narrow(s0r.a[i][m]);
+        for (int m = 0; m < R0; ++m) sr[(n1 + M * m) * D::NS + lg] = narrow(s0r.a[i][m]);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < D::I1; ++i) {
       const int b = tid + i * kThreadsL;
-      if (b < D::N1) {
-        const int l = b % kLT, mb = b / kLT;
-        const LineGeo<N, AX> g(tile, l);
-        const double s0 = g.s0(T.h);
+      const int l = b % kLT, mb = b / kLT;
+      if (b < D::N1 && !(packed_tile && l >= kLT - 2)) {
         double2 v[M];
 #pragma unroll
-        for (int k1 = 0; k1 < M; ++k1) {
-          const int f = mb + R0 * k1;
-          v[k1] = cscale(cmul(keep.v[i][k1], T.mp[f]), kappa_at(T.h, s0, f) * sc.inv_n * sc.half_dt_over_rho0);
-        }
+        for (int k1 = 0; k1 < M; ++k1)
+          v[k1] = cscale(cmul(keep.v[i][k1], T.mp[mb + R0 * k1]), sc.inv_n * sc.half_dt_over_rho0);
         dft_r<M, true>(v);
         s1_to_T<N>(L, v, l, mb);
       }
     }
+    if (packed_tile) packed_a<N, AX, NH>(L, Tg.kr, A, sc.inv_n * sc.half_dt_over_rho0, 2, tid, ps1, ps2);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < D::I0; ++i) {
@@ -390,7 +606,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
         T_to_s0_inv<N>(L, s0r.a[i], l, n1, T.tw);
 #pragma unroll
-        for (int m = 0; m < R0; ++m) su[(n1 + M * m) * D::NL + lg] = narrow(s0r.a[i][m]);
+        for (int m = 0; m < R0; ++m) su[(n1 + M * m) * D::NS + lg] = narrow(s0r.a[i][m]);
       }
     }
     return;
@@ -438,12 +654,23 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
   __syncthreads();
 
   if constexpr (MODE == LM_ADJ_FINAL) {
-    // out = F(rho^) / (3 c0^2) - dt/(2 rho0) m- F(v)
-    S1Reg<N> s1;
+    // out = F(rho^) / (3 c0^2) - dt/(2 rho0) m- F(v); s2: the second line of a packed slot
+    S1Reg<N> s1, s2;
+    if (packed_tile) {
+      packed_spectra<N>(L, tid);
+      __syncthreads();
+    }
 #pragma unroll
     for (int i = 0; i < D::I1; ++i) {
       const int b = tid + i * kThreadsL;
-      if (b < D::N1) T_to_s1_fwd<N>(L, s1.v[i], b % kLT, b / kLT);
+      if (b < D::N1) {
+        const int l = b % kLT, mb = b / kLT;
+        T_to_s1_fwd<N>(L, s1.v[i], l, mb);
+        if (packed_tile && l >= kLT - 2) {
+#pragma unroll
+          for (int k1 = 0; k1 < M; ++k1) packed_split<N>(L, l - (kLT - 2), mb + R0 * k1, s1.v[i][k1], s2.v[i][k1]);
+        }
+      }
     }
     if (reads) {
       __syncthreads();
@@ -453,25 +680,42 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         if (b < D::N0) {
           const int l = b % kLT, n1 = b / kLT, lg = tile * kLT + l;
 #pragma unroll
-          for (int m = 0; m < R0; ++m) s0r.a[i][m] = widen<double2>(su[(n1 + M * m) * D::NL + lg]);
+          for (int m = 0; m < R0; ++m) s0r.a[i][m] = widen<double2>(su[(n1 + M * m) * D::NS + lg]);
           s0_fwd_to_T<N>(L, s0r.a[i], l, n1, T.tw);
         }
       }
       __syncthreads();
+      if (packed_tile) {
+        packed_spectra<N>(L, tid);
+        __syncthreads();
+      }
 #pragma unroll
       for (int i = 0; i < D::I1; ++i) {
         const int b = tid + i * kThreadsL;
         if (b < D::N1) {
           const int l = b % kLT, mb = b / kLT;
-          const LineGeo<N, AX> g(tile, l);
+          const LineGeo<N, AX> g(tile * kLT + l);
           const double s0 = g.s0(T.h);
           double2 w[M];
           T_to_s1_fwd<N>(L, w, l, mb);
+          if (g.kind == 2) {
+            const int r = l - (kLT - 2);
+            const double *k1r = Tg.kr + kr_row(r, 0) * N, *k2r = Tg.kr + kr_row(r, 1) * N;
 #pragma unroll
-          for (int k1 = 0; k1 < M; ++k1) {
-            const int f = mb + R0 * k1;
-            const double2 t = cscale(cmul(w[k1], T.mm[f]), kappa_at(T.h, s0, f) * sc.half_dt_over_rho0);
-            s1.v[i][k1] = csub(s1.v[i][k1], t);
+            for (int k1 = 0; k1 < M; ++k1) {
+              const int f = mb + R0 * k1;
+              double2 w1, w2;
+              packed_split<N>(L, r, f, w1, w2);
+              s1.v[i][k1] = csub(s1.v[i][k1], cscale(cmul(w1, T.mm[f]), k1r[f] * sc.half_dt_over_rho0));
+              s2.v[i][k1] = csub(s2.v[i][k1], cscale(cmul(w2, T.mm[f]), k2r[f] * sc.half_dt_over_rho0));
+            }
+          } else {
+#pragma unroll
+            for (int k1 = 0; k1 < M; ++k1) {
+              const int f = mb + R0 * k1;
+              const double2 t = cscale(cmul(w[k1], T.mm[f]), kappa_at(T.h, s0, f) * sc.half_dt_over_rho0);
+              s1.v[i][k1] = csub(s1.v[i][k1], t);
+            }
           }
         }
       }
@@ -481,9 +725,14 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
       const int b = tid + i * kThreadsL;
       if (b < D::N1) {
         const int l = b % kLT, mb = b / kLT;
-        const LineGeo<N, AX> g(tile, l);
+        const LineGeo<N, AX> g(tile * kLT + l);
 #pragma unroll
         for (int k1 = 0; k1 < M; ++k1) hub_store<N, AX>(A.hout[AX], g, mb + R0 * k1, M * mb + k1, s1.v[i][k1]);
+        if (g.kind == 2) {
+          const LineGeo<N, AX> g2 = g.second();
+#pragma unroll
+          for (int k1 = 0; k1 < M; ++k1) hub_store<N, AX>(A.hout[AX], g2, mb + R0 * k1, M * mb + k1, s2.v[i][k1]);
+        }
       }
     }
     return;
@@ -493,9 +742,9 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
 #pragma unroll 1
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
-    if (b < D::N1) {
-      const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l);
+    const int l = b % kLT, mb = b / kLT;
+    if (b < D::N1 && !(packed_tile && l >= kLT - 2)) {
+      const LineGeo<N, AX> g(tile * kLT + l);
       const double s0 = g.s0(T.h);
       double2 v[M];
       T_to_s1_fwd<N>(L, v, l, mb);
@@ -508,6 +757,7 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
       s1_to_T<N>(L, v, l, mb);
     }
   }
+  if (__builtin_expect(packed_tile, 0)) packed_c<N>(L, Tg.kr, ADJ, sc.inv_n, tid);
   __syncthreads();
 
   // (D) second update, forward stage 0
@@ -548,9 +798,9 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
 #pragma unroll 1
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
-    if (b < D::N1) {
-      const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, AX> g(tile, l);
+    const int l = b % kLT, mb = b / kLT;
+    if (b < D::N1 && !(packed_tile && l >= kLT - 2)) {
+      const LineGeo<N, AX> g(tile * kLT + l);
       const double s0 = g.s0(T.h);
       double2 v[M];
       T_to_s1_fwd<N>(L, v, l, mb);
@@ -563,16 +813,35 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
       }
     }
   }
+  if (__builtin_expect(packed_tile, 0)) packed_e<N, AX>(L, Tg.kr, ADJ, A.hout[AX], tid);
 
   if (want_plane) {   // sum over kz of the hub read: the plane z = 0 of the pressure, / N^3
     __syncthreads();
     tput(L.T[tid], psum);
+    if (tid < 2 * R0) {
+      tput(L.T[kThreadsL + tid], ps1);
+      tput(L.T[kThreadsL + 2 * R0 + tid], ps2);
+    }
     __syncthreads();
     if (tid < kLT) {
       double2 s = make_double2(0.0, 0.0);
 #pragma unroll
       for (int j = 0; j < kThreadsL / kLT; ++j) s = cadd(s, tget(L.T[tid + kLT * j]));
-      A.plane[tile * kLT + tid] = narrow(cscale(s, sc.inv_ntot));
+      const LineGeo<N, AX> g(tile * kLT + tid);
+      if (g.kind == 2) {   // a packed pair: the sums of the packed_a threads of pair r
+        const int r = tid - (kLT - 2);
+        double2 s2 = make_double2(0.0, 0.0);
+        s = s2;
+        for (int j = 0; j < R0; ++j) {
+          s = cadd(s, tget(L.T[kThreadsL + r * R0 + j]));
+          s2 = cadd(s2, tget(L.T[kThreadsL + 2 * R0 + r * R0 + j]));
+        }
+        const LineGeo<N, AX> g2 = g.second();
+        A.plane[g2.kx * N + g2.kyp] = narrow(cscale(s2, sc.inv_ntot));
+      }
+      s = cscale(s, sc.inv_ntot);
+      A.plane[g.kx * N + g.kyp] = narrow(s);
+      if (g.kind == 1) A.plane[g.kx * N + g.kyn] = make_float2((float)s.x, (float)-s.y);
     }
   }
 }
@@ -582,9 +851,10 @@ __global__ __launch_bounds__(kThreadsL, MODE == LM_ADJ_FINAL ? 1 : PAT_LINE_WAVE
     LineTables T, LineScalars sc, LineBuffers B, LineStepArgs A) {
   __shared__ LineLds<N> L;
   const int tid = threadIdx.x;
-  // the three axes interleaved in dispatch order: the shorter z tiles mix into
-  // the first round of blocks instead of forming the second alone
-  const int ax = blockIdx.x % 3, tile = blockIdx.x / 3;
+  // the three axes interleaved in dispatch order, tiles in reverse: the last
+  // tile of each axis, which also carries the packed real pairs (a longer
+  // path), starts first
+  const int ax = blockIdx.x % 3, tile = LD<N>::NT - 1 - (int)blockIdx.x / 3;
   if (ax == 0) line_tile<N, 0, MODE, NH>(L, T, sc, B, A, tile, tid);
   else if (ax == 1) line_tile<N, 1, MODE, NH>(L, T, sc, B, A, tile, tid);
   else line_tile<N, 2, MODE, NH>(L, T, sc, B, A, tile, tid);
@@ -615,7 +885,7 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zfwd(LineTables T, const flo
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, 2> g(tile, l);
+      const LineGeo<N, 2> g = LineGeo<N, 2>::zline(tile * kLT + l);
       double2 v[D::M];
       T_to_s1_fwd<N>(L, v, l, mb);
 #pragma unroll
@@ -638,7 +908,7 @@ __global__ __launch_bounds__(kThreadsL) void k_line_zinv(LineTables T, const flo
     const int b = tid + i * kThreadsL;
     if (b < D::N1) {
       const int l = b % kLT, mb = b / kLT;
-      const LineGeo<N, 2> g(tile, l);
+      const LineGeo<N, 2> g = LineGeo<N, 2>::zline(tile * kLT + l);
       double2 v[D::M];
 #pragma unroll
       for (int k1 = 0; k1 < D::M; ++k1)
@@ -695,7 +965,7 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
   LineStepArgs A{};
   A.hin[0] = B.hub[0][0];
   A.hscale = sc.c2;
-  if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
   for (int n = 0; n + 1 < nt; ++n) {
     const int cur = n & 1;
     for (int c = 0; c < 3; ++c) {
@@ -704,8 +974,8 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
     }
     A.plane = B.planes + (size_t)n * D::NL;
     timed(kt, K_LINE_FWD, st, [&] {
-      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_FWD_STEP, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_FWD_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   const int last = (nt - 1) & 1;
@@ -736,8 +1006,8 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
     }
     A.src = B.planes + (size_t)(n + 1) * D::NL;
     timed(kt, K_LINE_ADJ, st, [&] {
-      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_ADJ_STEP, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+      else k_line<N, LM_ADJ_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
     });
   }
   cur = (nt - 1) & 1;
@@ -746,8 +1016,8 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
     A.hout[c] = B.hub[cur ^ 1][c];
   }
   A.src = B.planes;
-  if (nt == 1) k_line<N, LM_ADJ_FINAL, 0><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
-  else k_line<N, LM_ADJ_FINAL, 3><<<3 * D::NTILE, kThreadsL, 0, st>>>(T, sc, B, A);
+  if (nt == 1) k_line<N, LM_ADJ_FINAL, 0><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+  else k_line<N, LM_ADJ_FINAL, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
   k_line_zinv<N><<<D::NTILE, kThreadsL, 0, st>>>(T, B.hub[cur ^ 1][0], B.hub[cur ^ 1][1], B.hub[cur ^ 1][2], B.spec,
                                                  sc.inv_ntot);
   e = hipGetLastError();

@@ -257,6 +257,15 @@ pat_status build_tables(pat_plan* P, const pat_sampling* s) {
   const double hs = g.c0 * g.dt / 2.0;
   const size_t o_lh = r.size();
   for (int k = 0; k < NX; ++k) r.push_back(hs * wavenumber(k, NX, g.dx));
+  // sinc(c0 dt |k| / 2) along the real lines of the line propagator, whose
+  // transverse offset has |k_perp|^2 = c k_N^2 (k_N the Nyquist wavenumber), c = 0, 1, 2
+  const size_t o_lkr = r.size();
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < NX; ++k) {
+      const double hn = hs * wavenumber(NX / 2, NX, g.dx), hk = hs * wavenumber(k, NX, g.dx);
+      const double h = std::sqrt(c * hn * hn + hk * hk);
+      r.push_back(h > 0.0 ? std::sin(h) / h : 1.0);
+    }
   const size_t o_hx = r.size();
   for (int kx = 0; kx < NKX; ++kx) r.push_back(hs * wavenumber(kx, NX, g.dx));
   const size_t o_hy = r.size();
@@ -340,6 +349,7 @@ pat_status build_tables(pat_plan* P, const pat_sampling* s) {
     lt.mp = dc + o_lmp;
     lt.mm = dc + o_lmm;
     lt.h = dr + o_lh;
+    lt.kr = dr + o_lkr;
     lt.tw = dc + o_twz;
     lt.a[0] = t.ax; lt.a[1] = t.ay; lt.a[2] = t.az;
     lt.b[0] = t.bx; lt.b[1] = t.by; lt.b[2] = t.bz;
@@ -877,10 +887,10 @@ pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char**
   static const char* kNames[K_COUNT] = {"k_zgrad", "k_fwd_u",   "k_zmul<div>", "k_fwd_rho", "k_zmul<grad>",
                                         "k_adj_u", "k_zdiv_sum", "k_adj_rho",   "k_line<fwd>", "k_line<adj>"};
   // algorithmic HBM bytes per launch in units of C (one slab-spectrum field) and R (one real field);
-  // a line step reads the three hub spectra and both states and writes both states and its output,
-  // for each of the three components
-  static const int kC[K_COUNT] = {4, 5, 6, 5, 6, 6, 4, 4, 24, 24};
-  static const int kR[K_COUNT] = {0, 6, 0, 6, 0, 6, 0, 6, 0, 0};
+  // a line step, per component: its lines (N^3/2 complex values, R bytes) of the three hub
+  // spectra read, both states read and written, and one full output spectrum (C) written
+  static const int kC[K_COUNT] = {4, 5, 6, 5, 6, 6, 4, 4, 3, 3};
+  static const int kR[K_COUNT] = {0, 6, 0, 6, 0, 6, 0, 6, 21, 21};
   PAT_TRY(check_plan(plan));
   if (kernel_id < 0 || kernel_id >= K_COUNT) return set_error(PAT_ERR_INVALID, "pat_kernel_info: bad kernel_id");
   const double C = (double)n_spec(plan->g) * sizeof(float2), R = (double)n_voxels(plan->g) * sizeof(float);

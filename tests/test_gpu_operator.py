@@ -67,6 +67,46 @@ def test_adjoint_matches_oracle(n, nt, kind, pml, scheme):
     assert err < TOL_OP
 
 
+def _special_volume(n, seed):
+    """A volume made only of what the line layout treats apart: fields constant
+    or alternating along x or y or z (spectra on the planes kx, ky or kz = 0 or
+    N/2, where only one line of each conjugate pair is stored), among them the
+    four real z lines kx, ky in {0, N/2} that share two slots."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    v = np.zeros((n, n, n))
+    for ax in (0, 1):
+        for ay in (0, 1):
+            v += (-1.0) ** (ax * x + ay * y) * rng.standard_normal(n)[z]
+    for a in (0, 1):
+        v += (-1.0) ** (a * z) * rng.standard_normal((n, n))[y, x]
+        v += (-1.0) ** (a * x) * rng.standard_normal((n, n))[z, y]
+        v += (-1.0) ** (a * y) * rng.standard_normal((n, n))[z, x]
+    return v
+
+
+@pytest.mark.parametrize("n,nt,pml", [(16, 40, 4), (32, 60, 8)])
+def test_line_layout_special_planes(n, nt, pml):
+    """Forward of a volume, and adjoint of data, that live only on the
+    self-conjugate planes and real lines (full sampling): line scheme vs FP64."""
+    got, ref = _fwd_case(n, nt, "full", pml, x=_special_volume(n, 11))
+    e1 = rel_l2(got, ref)
+    rng = np.random.default_rng(12)
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    y = sum((-1.0) ** (ax * xx + ay * yy)[None] * rng.standard_normal(nt)[:, None, None]
+            for ax in (0, 1) for ay in (0, 1)).reshape(nt, n * n)
+    g = oracle_grid(n, nt, pml)
+    smp = oracle_sampling("full", n)
+    ref = oracle.WaveOperator(g).adjoint_planes(apply_ct(y, smp, n, n))
+    from paper_1605_00133_amd import pat as P
+    plan = gpu_plan(n, nt, smp, pml)
+    p = empty(plan.vol_shape)
+    P.pat_adjoint(plan, to_dev(y), p)
+    e2 = rel_l2(to_host(p), ref)
+    print(f"special planes {n}^3 nt={nt}: forward {e1:.3e}, adjoint {e2:.3e}")
+    assert e1 < TOL_OP and e2 < TOL_OP
+
+
 @pytest.mark.parametrize("kind", ["points", "hadamard"])
 def test_fp32_butterfly_variant(kind):
     """The FP32-arithmetic variant of the propagator (pat_plan_set_fft_precision(32)) at 32^3."""

@@ -390,7 +390,7 @@ __device__ __forceinline__ void packed_a(LineLds<N>& L, const double* kr, const 
 #pragma unroll
         for (int c = 0; c < NH; ++c) P = cadd(P, widen<double2>(A.hin[c][idx]));
         if (cj) P.y = -P.y;
-        P = cscale(P, A.hscale);
+        P = cscale(P, kind == 3 && NH > 0 ? kap[f] * A.hscale : A.hscale);
         if (kind == 3) {
           double2 S = widen<double2>(A.src[src_addr<N, AX>(g, f, p, cj)]);
           if (cj) S.y = -S.y;
@@ -439,20 +439,12 @@ __device__ __forceinline__ void packed_c(LineLds<N>& L, const double* kr, bool a
   }
 }
 
-// packed_e: the output spectra of both lines (adjoint: each times m- and its
-// sinc). Every thread of the block calls it.
+// packed_e: the output spectra of both lines (adjoint: times m-). Every thread
+// of the block calls it.
 template <int N, int AX>
-__device__ __forceinline__ void packed_e(LineLds<N>& L, const double* kr, bool adj, float2* out, int tid) {
+__device__ __forceinline__ void packed_e(LineLds<N>& L, bool adj, float2* out, int tid) {
   using D = LD<N>;
   const int r = tid / D::R0 % 2, mb = tid % D::R0;
-  double ka[D::M], kb[D::M];
-  if (adj) {   // the sinc values first: their loads are in flight across the exchange
-#pragma unroll
-    for (int k1 = 0; k1 < D::M; ++k1) {
-      ka[k1] = kr[kr_row(r, 0) * N + mb + D::R0 * k1];
-      kb[k1] = kr[kr_row(r, 1) * N + mb + D::R0 * k1];
-    }
-  }
   packed_spectra<N>(L, tid);
   __syncthreads();
   if (tid < 2 * D::R0) {
@@ -464,8 +456,8 @@ __device__ __forceinline__ void packed_e(LineLds<N>& L, const double* kr, bool a
       double2 z1, z2;
       packed_split<N>(L, r, f, z1, z2);
       if (adj) {
-        z1 = cscale(cmul(z1, L.mm[f]), ka[k1]);
-        z2 = cscale(cmul(z2, L.mm[f]), kb[k1]);
+        z1 = cmul(z1, L.mm[f]);
+        z2 = cmul(z2, L.mm[f]);
       }
       hub_store<N, AX>(out, g, f, p, z1);
       hub_store<N, AX>(out, g2, f, p, z2);
@@ -545,7 +537,8 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
         for (int c = 0; c < NH; ++c) P = cadd(P, widen<double2>(hv[k1][c]));
         const bool cj = AX == 0 && f > D::H;
         if (cj) P.y = -P.y;
-        P = cscale(P, A.hscale);
+        // adjoint: the stored outputs are m-_c W_c; their sum takes the sinc here
+        P = cscale(P, ADJ && NH > 0 ? kappa_at(T.h, s0, f) * A.hscale : A.hscale);
         if (ADJ) {
           double2 S = widen<double2>(sv[k1]);
           if (cj) S.y = -S.y;
@@ -794,26 +787,24 @@ __device__ __forceinline__ void line_tile(LineLds<N>& L, const LineTables& Tg, c
   }
   __syncthreads();
 
-  // (E) forward stage 1 and the output spectrum (adjoint: times m-)
+  // (E) forward stage 1 and the output spectrum (adjoint: times m-; the
+  // reader applies the sinc, common to the three components)
 #pragma unroll 1
   for (int i = 0; i < D::I1; ++i) {
     const int b = tid + i * kThreadsL;
     const int l = b % kLT, mb = b / kLT;
     if (b < D::N1 && !(packed_tile && l >= kLT - 2)) {
       const LineGeo<N, AX> g(tile * kLT + l);
-      const double s0 = g.s0(T.h);
       double2 v[M];
       T_to_s1_fwd<N>(L, v, l, mb);
 #pragma unroll
       for (int k1 = 0; k1 < M; ++k1) {
         const int f = mb + R0 * k1, p = M * mb + k1;
-        double2 o = v[k1];
-        if (ADJ) o = cscale(cmul(o, T.mm[f]), kappa_at(T.h, s0, f));
-        hub_store<N, AX>(A.hout[AX], g, f, p, o);
+        hub_store<N, AX>(A.hout[AX], g, f, p, ADJ ? cmul(v[k1], T.mm[f]) : v[k1]);
       }
     }
   }
-  if (__builtin_expect(packed_tile, 0)) packed_e<N, AX>(L, Tg.kr, ADJ, A.hout[AX], tid);
+  if (__builtin_expect(packed_tile, 0)) packed_e<N, AX>(L, ADJ, A.hout[AX], tid);
 
   if (want_plane) {   // sum over kz of the hub read: the plane z = 0 of the pressure, / N^3
     __syncthreads();

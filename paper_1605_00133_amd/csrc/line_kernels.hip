@@ -116,7 +116,8 @@ __device__ __forceinline__ int hidx(int kz, int kx, int kyp) {
 //     outputs of its partner (kind 1)
 //   last two slots: the real lines (P, 0) and (P, N/2) of P = 0 and P = N/2,
 //     packed as line + i * second line (kind 2)
-// The x lines with 0 < kz < N/2 own the conjugates of their kx >= N/2 outputs too.
+// An x line that is not real also writes the conjugates of its kx = 0 and
+// kx >= N/2 outputs at (-kx, -ky, -kz) (the hub holds kx <= N/2 only).
 template <int N, int AX>
 struct LineGeo {
   int lg, kx, kyp, kz, kyf, kyn;   // kyf: natural ky of ky_pos, kyn: ky_pos of -ky

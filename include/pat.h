@@ -195,10 +195,13 @@ pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p,
 pat_status pat_psnr(pat_plan* plan, const float* p, const float* p_ref, double* out);
 
 /* Diagnostics: HIP-event timing of the propagator's kernels, for roofline
- * reporting. Between pat_profile_begin and pat_profile_end every launch of
+ * reporting. Between pat_profile_begin and pat_profile_end the launches of
  * kernel `kernel_id` (or of all of them, kernel_id = -2) made by pat_forward,
- * pat_adjoint and the solvers on this plan is bracketed by two events on the
- * plan's stream, up to max_launches launches. pat_profile_end syncs and fills
+ * pat_adjoint and the solvers on this plan are bracketed by events on the
+ * plan's stream: each launch by its own pair (slab scheme), or each run of
+ * consecutive time steps of one application by one pair counted as that many
+ * launches (line scheme: per-launch events would add their gaps to every
+ * step), up to max_launches records. pat_profile_end syncs and fills
  * total_ms[PAT_K_COUNT] and launches[PAT_K_COUNT] (host, either may be NULL). */
 typedef enum {
   PAT_K_ZGRAD = 0,      /* forward: z pass of the gradient (1 spectrum in, 2 out) */

@@ -958,6 +958,7 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
   A.hin[0] = B.hub[0][0];
   A.hscale = sc.c2;
   if (nt > 1) k_line<N, LM_FWD_INIT, 1><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+  const int rec = timed_span_begin(kt, K_LINE_FWD, st);
   for (int n = 0; n + 1 < nt; ++n) {
     const int cur = n & 1;
     for (int c = 0; c < 3; ++c) {
@@ -965,11 +966,10 @@ hipError_t line_forward(const LineTables& T, const LineScalars& sc, const LineBu
       A.hout[c] = B.hub[cur ^ 1][c];
     }
     A.plane = B.planes + (size_t)n * D::NL;
-    timed(kt, K_LINE_FWD, st, [&] {
-      if (n == 0) k_line<N, LM_FWD_STEP, 1><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_FWD_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
-    });
+    if (n == 0) k_line<N, LM_FWD_STEP, 1><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+    else k_line<N, LM_FWD_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
   }
+  timed_span_end(kt, rec, K_LINE_FWD, nt - 1, st);
   const int last = (nt - 1) & 1;
   k_line_plane<N><<<cdiv(D::NL, kThreadsL), kThreadsL, 0, st>>>(B.hub[last][0], B.hub[last][1], B.hub[last][2],
                                                                 nt == 1 ? 1 : 3,
@@ -989,6 +989,7 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
   LineStepArgs A{};
   A.hscale = sc.adj_scale;
   int cur = 0;
+  const int rec = timed_span_begin(kt, K_LINE_ADJ, st);
   for (int j = 0; j + 1 < nt; ++j) {   // iteration of time index n = nt - 2 - j
     const int n = nt - 2 - j;
     cur = j & 1;
@@ -997,11 +998,10 @@ hipError_t line_adjoint(const LineTables& T, const LineScalars& sc, const LineBu
       A.hout[c] = B.hub[cur ^ 1][c];
     }
     A.src = B.planes + (size_t)(n + 1) * D::NL;
-    timed(kt, K_LINE_ADJ, st, [&] {
-      if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
-      else k_line<N, LM_ADJ_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
-    });
+    if (j == 0) k_line<N, LM_ADJ_STEP, 0><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
+    else k_line<N, LM_ADJ_STEP, 3><<<3 * D::NT, kThreadsL, 0, st>>>(T, sc, B, A);
   }
+  timed_span_end(kt, rec, K_LINE_ADJ, nt - 1, st);
   cur = (nt - 1) & 1;
   for (int c = 0; c < 3; ++c) {
     A.hin[c] = B.hub[cur][c];

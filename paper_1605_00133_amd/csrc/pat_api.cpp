@@ -210,6 +210,7 @@ struct pat_plan {
   KernelTimer timer;        // active when timer.ev != nullptr
   std::vector<hipEvent_t> timer_events;
   std::vector<int> timer_ids;
+  std::vector<int> timer_nl;
 };
 
 namespace {
@@ -844,9 +845,11 @@ pat_status pat_profile_begin(pat_plan* plan, int32_t kernel_id, int32_t max_laun
     }
   }
   plan->timer_ids.assign(max_launches, -1);
+  plan->timer_nl.assign(max_launches, 1);
   plan->timer.which = kernel_id;
   plan->timer.ev = plan->timer_events.data();
   plan->timer.ids = plan->timer_ids.data();
+  plan->timer.nl = plan->timer_nl.data();
   plan->timer.cap = max_launches;
   plan->timer.count = 0;
   return PAT_OK;
@@ -869,11 +872,12 @@ pat_status pat_profile_end(pat_plan* plan, double* total_ms, int32_t* launches) 
       break;
     }
     tot[plan->timer.ids[i]] += ms;
-    cnt[plan->timer.ids[i]] += 1;
+    cnt[plan->timer.ids[i]] += plan->timer.nl[i];
   }
   for (hipEvent_t e : plan->timer_events) (void)hipEventDestroy(e);
   plan->timer_events.clear();
   plan->timer_ids.clear();
+  plan->timer_nl.clear();
   plan->timer = KernelTimer{};
   if (st != PAT_OK) return st;
   for (int k = 0; k < K_COUNT; ++k) {

@@ -75,8 +75,9 @@ enum KernelId {
 // Optional HIP-event bracketing of kernel launches (which = id, or -2 for all).
 struct KernelTimer {
   int which;
-  hipEvent_t* ev;   // 2 per recorded launch
-  int* ids;         // kernel id of each recorded launch
+  hipEvent_t* ev;   // 2 per record
+  int* ids;         // kernel id of each record
+  int* nl;          // launches a record spans
   int cap;
   int count;
 };
@@ -90,8 +91,26 @@ inline void timed(KernelTimer* kt, int id, hipStream_t st, F&& launch) {
   if (on) {
     (void)hipEventRecord(kt->ev[2 * kt->count + 1], st);
     kt->ids[kt->count] = id;
+    kt->nl[kt->count] = 1;
     kt->count++;
   }
+}
+
+// A run of `launches` consecutive launches of kernel id with nothing else on
+// the stream between them (the time steps of one application), bracketed by
+// one pair of events: per-launch events add their own gaps to every launch.
+// timed_span_begin returns the record index, or -1 when not recording.
+inline int timed_span_begin(KernelTimer* kt, int id, hipStream_t st) {
+  const bool on = kt && (kt->which == id || kt->which == -2) && kt->count < kt->cap;
+  if (!on) return -1;
+  (void)hipEventRecord(kt->ev[2 * kt->count], st);
+  return kt->count++;
+}
+inline void timed_span_end(KernelTimer* kt, int rec, int id, int launches, hipStream_t st) {
+  if (rec < 0) return;
+  (void)hipEventRecord(kt->ev[2 * rec + 1], st);
+  kt->ids[rec] = id;
+  kt->nl[rec] = launches;
 }
 
 // Hand-off flags of the slab-pair velocity passes (device, >= nz entries, zero

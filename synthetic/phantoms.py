@@ -49,16 +49,13 @@ def _smooth(vol, sigma=0.7, taps=7):
     return out
 
 
-def vessel_phantom(shape, pml, n_vessels, r_min, r_max, seed, smooth=True):
-    """[nz][ny][nx] nonnegative FP64 phantom."""
-    rng = np.random.default_rng(seed)
+def _draw_vessels(rng, shape, pml, n_vessels, r_min, r_max):
     lo, hi = _interior(shape, pml)
     lo_s = lo + (r_max + 2.0)
     hi_s = hi - (r_max + 2.0)
     hi_s = np.maximum(hi_s, lo_s)
     width = float(np.min(hi - lo))
-    vol = np.zeros(shape)
-    zz, yy, xx = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    vessels = []
     for _ in range(n_vessels):
         amp = rng.uniform(0.5, 1.0)
         rad = rng.uniform(r_min, r_max)
@@ -68,18 +65,67 @@ def vessel_phantom(shape, pml, n_vessels, r_min, r_max, seed, smooth=True):
             d /= np.linalg.norm(d)
             length = rng.uniform(0.25, 0.5) * width
             pts.append(np.clip(pts[-1] + length * d, lo_s, hi_s))
+        vessels.append((amp, rad, pts))
+    return vessels
+
+
+def _rasterize(shape, vessels, offset=(0.0, 0.0, 0.0), amps=None):
+    vol = np.zeros(shape)
+    zz, yy, xx = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    off = np.asarray(offset, dtype=np.float64)
+    for v, (amp, rad, pts) in enumerate(vessels):
+        amp = amp if amps is None else amps[v]
         for a, b in zip(pts[:-1], pts[1:]):
+            a, b = a + off, b + off
             bl = np.floor(np.minimum(a, b) - rad - 1).astype(int)
             bh = np.ceil(np.maximum(a, b) + rad + 1).astype(int) + 1
             bl = np.maximum(bl, 0)
             bh = np.minimum(bh, np.array(shape))
+            if np.any(bh <= bl):
+                continue
             sl = tuple(slice(l, h) for l, h in zip(bl, bh))
             grid_pts = np.stack([zz[sl].ravel(), yy[sl].ravel(), xx[sl].ravel()], axis=1)
             inside = (_segment_dist(grid_pts, a, b) <= rad).reshape(zz[sl].shape)
             vol[sl] = np.maximum(vol[sl], amp * inside)
+    return vol
+
+
+def vessel_phantom(shape, pml, n_vessels, r_min, r_max, seed, smooth=True):
+    """[nz][ny][nx] nonnegative FP64 phantom."""
+    rng = np.random.default_rng(seed)
+    vol = _rasterize(shape, _draw_vessels(rng, shape, pml, n_vessels, r_min, r_max))
     if smooth:
         vol = _smooth(vol)
     return np.maximum(vol, 0.0)
+
+
+def moving_vessel_frames(shape, pml, n_frames, n_vessels, r_min, r_max, seed, shift=1.0, pulse=0.1, period=8):
+    """Frames of a moving vessel phantom (a dynamic scan): the vessels of
+    vessel_phantom(shape, pml, n_vessels, r_min, r_max, seed) translated rigidly
+    by `shift` voxels per frame along a seeded direction parallel to the sensor
+    plane (reversing at the interior's edge), each vessel's amplitude pulsating
+    as 1 + pulse * sin(2 pi t / period + phase_v) with a seeded phase. Voxels
+    closer than 3 to the PML or to the sensor layer are cleared before the
+    smoothing, so every frame stays inside the interior. Returns a list of
+    [nz][ny][nx] FP64 volumes."""
+    rng = np.random.default_rng(seed)
+    vessels = _draw_vessels(rng, shape, pml, n_vessels, r_min, r_max)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_vessels)
+    ang = rng.uniform(0.0, 2.0 * np.pi)
+    direction = np.array([0.0, np.sin(ang), np.cos(ang)])
+    lo, hi = _interior(shape, pml)
+    keep = np.zeros(shape, dtype=bool)
+    keep[tuple(slice(int(l) + 3, int(h) - 2) for l, h in zip(lo, hi))] = True
+    span = 8.0 * shift
+    frames = []
+    for t in range(n_frames):
+        s = (t * shift) % (2.0 * span) if span > 0 else 0.0
+        s = s if s <= span else 2.0 * span - s   # back and forth over `span` voxels
+        amps = [amp * (1.0 + pulse * np.sin(2.0 * np.pi * t / period + phase[v]))
+                for v, (amp, _, _) in enumerate(vessels)]
+        vol = _rasterize(shape, vessels, s * direction, amps) * keep
+        frames.append(np.maximum(_smooth(vol), 0.0))
+    return frames
 
 
 def gaussian_volume(shape, seed):

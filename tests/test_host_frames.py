@@ -1,0 +1,30 @@
+"""Frames of the synthetic dynamic scan (synthetic.moving_vessel_frames)."""
+
+import numpy as np
+
+from synthetic import moving_vessel_frames, vessel_phantom
+
+
+def test_static_frames_are_identical_and_inside_the_interior():
+    fr = moving_vessel_frames((32, 32, 32), 8, 3, 6, 1.0, 2.0, 5, shift=0.0, pulse=0.0)
+    assert all(np.array_equal(fr[0], f) for f in fr[1:])
+    f = fr[0]
+    assert f.min() >= 0.0 and f.max() > 0.3
+    assert not f[:, :8].any() and not f[:, -8:].any() and not f[:, :, :8].any() and not f[:, :, -8:].any()
+    assert not f[0].any() and not f[-16:].any()   # sensor layer and the far PML stay clear
+
+
+def test_moving_frames_move_and_pulsate():
+    fr = moving_vessel_frames((32, 32, 32), 8, 4, 6, 1.0, 2.0, 5)
+    assert len(fr) == 4
+    assert all(not np.array_equal(fr[0], f) for f in fr[1:])
+    still = moving_vessel_frames((32, 32, 32), 8, 4, 6, 1.0, 2.0, 5, shift=0.0)
+    # without motion only amplitudes change: the support stays the same
+    assert all(np.array_equal(still[0] > 0, f > 0) for f in still[1:])
+
+
+def test_vessels_are_those_of_vessel_phantom():
+    # one frame, no motion or pulsation: the phantom's vessels, cut to the interior
+    a = moving_vessel_frames((32, 32, 32), 8, 1, 6, 1.0, 2.0, 1, shift=0.0, pulse=0.0)[0]
+    b = vessel_phantom((32, 32, 32), 8, 6, 1.0, 2.0, 1)
+    assert np.abs(a - b).max() < 0.5 and np.abs(a - b).sum() < 0.05 * b.sum()

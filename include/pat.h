@@ -185,7 +185,10 @@ typedef struct {
 } pat_recon_report;
 
 /* TV+ (n_outer = 1) or TV+Br reconstruction of p from f (device [nt][mc]) into p
- * (device volume). Syncs once per FISTA iteration to read the FP64 energy. */
+ * (device volume; output only: the first FISTA loop starts from p = 0, whose
+ * residual is -f without an operator application, and each Bregman step from
+ * the previous one's result). Syncs once per FISTA iteration to read the FP64
+ * energy. */
 pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p,
                            const pat_recon_params* params, pat_recon_report* report);
 

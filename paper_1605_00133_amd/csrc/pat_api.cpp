@@ -754,8 +754,12 @@ pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p, const pat_r
   for (int k = 0; k < prm->n_outer; ++k) {
     // d = f + b^k ; FISTA from x0 = current p (held in xp)
     PAT_TRY_HIP(launch_axpy(f, b, d, 1.f, nd, st));
-    PAT_TRY(op_forward(plan, xp, tmp));
-    PAT_TRY_HIP(launch_axpy(tmp, d, rp, -1.f, nd, st));        // r_prev = C A x0 - d
+    if (k == 0) {
+      PAT_TRY_HIP(launch_scale(d, rp, -1.f, nd, st));          // x0 = 0, so C A x0 = 0 and r_prev = -d
+    } else {
+      PAT_TRY(op_forward(plan, xp, tmp));
+      PAT_TRY_HIP(launch_axpy(tmp, d, rp, -1.f, nd, st));      // r_prev = C A x0 - d
+    }
     double e_prev, tv, res;
     PAT_TRY(energy(rp, xp, &e_prev, &tv, &res));
     PAT_TRY_HIP(hipMemcpyAsync(y, xp, nv * sizeof(float), hipMemcpyDeviceToDevice, st));

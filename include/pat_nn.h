@@ -1,0 +1,75 @@
+/*
+ * pat_nn.h -- C ABI of the network layers of a learned update step.
+ *
+ * Not part of the paper's method: a small 3D convolutional network that maps
+ * the current iterate p_k and the data-term gradient A^T C^T (C A p_k - f)
+ * (eq. BP, computed by pat_adjoint) to the next iterate. These entry points
+ * are its building blocks; the operator, the prox and the solver are in pat.h.
+ *
+ * Conventions (in addition to those of pat.h)
+ *  - Activations are float32 [batch][channels][nz][ny][nx] (x fastest);
+ *    convolution weights are float32 [c_out][c_in][3][3][3], biases [c_out].
+ *    The convolution is a cross-correlation with one voxel of zero padding
+ *    (output size = input size): y[co][z,y,x] = sum over ci and dz, dy, dx in
+ *    {-1, 0, 1} of w[co][ci][dz+1][dy+1][dx+1] x[ci][z+dz, y+dy, x+dx].
+ *  - Every operand of a product (activations, weights, gradients) is rounded
+ *    to bfloat16 (nearest even) as it enters the matrix cores; products are
+ *    summed in FP32 (weight gradients: FP32 per chunk of rows, chunks summed in
+ *    FP64). Biases are added in FP32. Results are deterministic.
+ *  - All pointers are device pointers unless stated otherwise, owned by the
+ *    caller; `stream` is a hipStream_t (NULL: the default stream). Work is
+ *    enqueued asynchronously; arguments are validated before anything is
+ *    enqueued. Errors: PAT_ERR_INVALID (null pointer, non-positive size, too
+ *    large), PAT_ERR_NOMEM (workspace too small), PAT_ERR_HIP (launch failed);
+ *    pat_last_error() gives the message. batch = 0 enqueues nothing (the
+ *    weight gradient then writes zeros).
+ */
+#ifndef PAT_NN_H
+#define PAT_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "pat.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* y = conv(x, w) + bias (bias may be NULL), then max(y, 0) if relu != 0.
+ * x [batch][c_in][nz][ny][nx], y [batch][c_out][nz][ny][nx]; x and y must not overlap. */
+pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias, float* y, int32_t batch,
+                              int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
+                              void* stream);
+
+/* dx = gradient of sum(dy * conv(x, w)) with respect to x: the adjoint of the
+ * convolution (weights transposed over channels, taps mirrored).
+ * dy [batch][c_out][...], dx [batch][c_in][...] (overwritten); no overlap. */
+pat_status pat_conv3d_backward_input(const float* dy, const float* w, float* dx, int32_t batch, int32_t c_in,
+                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* stream);
+
+/* Bytes of device workspace pat_conv3d_backward_weight needs for these sizes
+ * (0 for invalid sizes). */
+size_t pat_conv3d_backward_weight_workspace_bytes(int32_t batch, int32_t c_in, int32_t c_out, int32_t nz, int32_t ny,
+                                                  int32_t nx);
+
+/* dw[co][ci][tap] = sum over batch and voxels of dy[co][v] x[ci][v + d(tap)]
+ * and dbias[co] = sum of dy[co] (dbias may be NULL); both overwritten.
+ * workspace: device buffer of at least the bytes above, used as scratch. */
+pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw, float* dbias, int32_t batch,
+                                      int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx,
+                                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* grad[i] = 0 where y[i] <= 0 (or NaN), in place: the ReLU's backward given its output y. */
+pat_status pat_relu_backward(const float* y, float* grad, int64_t n, void* stream);
+
+/* One Adam step on n parameters (step = 1, 2, ...): m and v are the moment
+ * buffers (start at zero), updated in place with w. */
+pat_status pat_adam_step(float* w, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int32_t step, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_NN_H */

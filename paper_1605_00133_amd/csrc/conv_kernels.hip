@@ -1,0 +1,324 @@
+// 3x3x3 convolution layers for a learned update step (outside the paper's
+// method: a network mapping the iterate and the gradient A^T C^T (C A p - f)
+// of eq. BP to the next iterate). BF16 operands on the matrix cores
+// (v_mfma_f32_16x16x16_bf16), FP32 accumulation, FP32 tensors in HBM.
+//
+// Layout: activations [B][C][nz][ny][nx] (x fastest), weights [Co][Ci][3][3][3],
+// zero padding of one voxel ("same" size). Every entry point is a GEMM over
+// K = 27 Ci (k = ci * 27 + tap, tap = 9 (dz+1) + 3 (dy+1) + (dx+1)):
+//   forward       y[b][co][v]  = sum_k w[co][k] x[b][ci][v + d(tap)] (+ bias, ReLU)
+//   input grad    dx[b][ci][v] = sum_{co,tap} w[co][ci][tap] dy[b][co][v - d(tap)]
+//                 (the forward with w transposed over channels and the taps mirrored)
+//   weight grad   dw[co][k]    = sum_{b,v} dy[b][co][v] x[b][ci][v + d(tap)], db[co] = sum dy
+//
+// MFMA 16x16x16 (64 lanes, lane l, r = l & 15, q = l >> 4): A operand rows
+// r, columns 4q..4q+3; B operand rows 4q..4q+3, column r; result rows 4q..4q+3
+// (one per accumulator register), column r. Each operand value is rounded to
+// BF16 (nearest even) when it is loaded; sums stay FP32. The weight gradient
+// writes one 16x16 partial per (chunk of rows, tile) and sums the chunks in a
+// fixed order in FP64: results do not depend on scheduling.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/pat_nn.h"
+#include "pat_internal.hpp"
+
+#define PAT_NN_CHECK(expr)          \
+  do {                              \
+    const pat_status s_ = (expr);   \
+    if (s_ != PAT_OK) return s_;    \
+  } while (0)
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTaps = 27;
+constexpr int kWavesPerBlock = 4;
+constexpr int kChunks = 256;   // row chunks of the weight gradient
+
+__device__ __forceinline__ short bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u)   // Inf stays Inf, NaN stays a (quiet) NaN
+    return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ void tap_offset(int tap, int& dz, int& dy, int& dx) {
+  dz = tap / 9 - 1;
+  dy = (tap / 3) % 3 - 1;
+  dx = tap % 3 - 1;
+}
+
+// One wave: a 16 (x positions of one row) x 16 (output channels) tile.
+// TW: the input-gradient form (weights [cin][cout][27] read transposed and mirrored).
+template <bool TW>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d(
+    const float* __restrict__ x, const float* __restrict__ w, const float* __restrict__ bias,
+    float* __restrict__ y, int nb, int cin, int cout, int nz, int ny, int nx, int relu, int xtiles, int ctiles) {
+  const int lane = threadIdx.x & 63;
+  long t = (long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int xt = (int)(t % xtiles);
+  t /= xtiles;
+  const int ct = (int)(t % ctiles);
+  t /= ctiles;
+  const int yy = (int)(t % ny);
+  t /= ny;
+  const int zz = (int)(t % nz);
+  t /= nz;
+  const int b = (int)t;
+  if (b >= nb) return;   // wave-uniform: the grid is rounded up to whole blocks
+  const int r = lane & 15, q = lane >> 4;
+  const int x0 = xt * 16;
+  const int K = cin * kTaps;
+  const long vol = (long)nz * ny * nx;
+  const float* xb = x + (long)b * cin * vol;
+  const int co_b = ct * 16 + r;   // this lane's B column
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, bw;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + 4 * q + i;
+      float av = 0.f, bv = 0.f;
+      if (k < K) {
+        const int ci = k / kTaps, tap = k - ci * kTaps;
+        int dz, dy, dx;
+        tap_offset(tap, dz, dy, dx);
+        const int z2 = zz + dz, y2 = yy + dy, x2 = x0 + r + dx;
+        if (z2 >= 0 && z2 < nz && y2 >= 0 && y2 < ny && x2 >= 0 && x2 < nx)
+          av = xb[ci * vol + ((long)z2 * ny + y2) * nx + x2];
+        if (co_b < cout)
+          bv = TW ? w[((long)ci * cout + co_b) * kTaps + (kTaps - 1 - tap)] : w[((long)co_b * cin + ci) * kTaps + tap];
+      }
+      a[i] = bf16_rne(av);
+      bw[i] = bf16_rne(bv);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
+  }
+  if (co_b >= cout) return;
+  const float bb = bias ? bias[co_b] : 0.f;
+  float* yrow = y + ((long)b * cout + co_b) * vol + ((long)zz * ny + yy) * nx;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int xo = x0 + 4 * q + i;
+    if (xo < nx) {
+      float v = acc[i] + bb;
+      yrow[xo] = relu ? fmaxf(v, 0.f) : v;
+    }
+  }
+}
+
+// Weight (and bias) gradient partials: GEMM with M = co, N = k (27 cin taps, then one
+// column of ones for the bias), K = voxels. Wave (chunk, mt, nt) sums the rows
+// chunk, chunk + nchunk, ... of the B * nz * ny rows, 16 x positions at a time.
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d_wgrad_partial(
+    const float* __restrict__ x, const float* __restrict__ gy, float* __restrict__ part, int nb, int cin,
+    int cout, int nz, int ny, int nx, int nchunk, int mtiles, int ntiles) {
+  const int lane = threadIdx.x & 63;
+  long t = (long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int nt = (int)(t % ntiles);
+  t /= ntiles;
+  const int mt = (int)(t % mtiles);
+  t /= mtiles;
+  const int chunk = (int)t;
+  if (chunk >= nchunk) return;   // wave-uniform
+  const int r = lane & 15, q = lane >> 4;
+  const int ncol = cin * kTaps + 1;
+  const long vol = (long)nz * ny * nx;
+  const long rows = (long)nb * nz * ny;
+  const int co_a = mt * 16 + r;   // A row of this lane
+  const int kb = nt * 16 + r;     // B column of this lane
+  int ci = 0, dz = 0, dy = 0, dx = 0;
+  const bool wcol = kb < ncol - 1, bcol = kb == ncol - 1;
+  if (wcol) {
+    ci = kb / kTaps;
+    tap_offset(kb - ci * kTaps, dz, dy, dx);
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (long row = chunk; row < rows; row += nchunk) {
+    const int yy = (int)(row % ny);
+    const int zz = (int)((row / ny) % nz);
+    const int b = (int)(row / ((long)ny * nz));
+    const float* dyrow = gy + ((long)b * cout + co_a) * vol + ((long)zz * ny + yy) * nx;
+    const int z2 = zz + dz, y2 = yy + dy;
+    const bool rowin = wcol && z2 >= 0 && z2 < nz && y2 >= 0 && y2 < ny;
+    const float* xrow = x + ((long)b * cin + ci) * vol + ((long)(rowin ? z2 : 0) * ny + (rowin ? y2 : 0)) * nx;
+    for (int x0 = 0; x0 < nx; x0 += 16) {
+      bf16x4 a, bv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int xv = x0 + 4 * q + i;
+        float av = 0.f, bx = 0.f;
+        if (xv < nx) {
+          if (co_a < cout) av = dyrow[xv];
+          if (rowin) {
+            const int x2 = xv + dx;
+            if (x2 >= 0 && x2 < nx) bx = xrow[x2];
+          } else if (bcol) {
+            bx = 1.f;
+          }
+        }
+        a[i] = bf16_rne(av);
+        bv[i] = bf16_rne(bx);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+    }
+  }
+  if (kb >= ncol) return;
+  float* p = part + (long)chunk * cout * ncol;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int co = mt * 16 + 4 * q + i;
+    if (co < cout) p[(long)co * ncol + kb] = acc[i];
+  }
+}
+
+// dw[co][k] = sum over chunks in order (FP64); the last column goes to db.
+__global__ __launch_bounds__(256) void k_conv3d_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
+                                                             float* __restrict__ db, int cin, int cout, int nchunk) {
+  const int ncol = cin * kTaps + 1;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)cout * ncol) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(long)c * cout * ncol + i];
+  const int co = (int)(i / ncol), k = (int)(i % ncol);
+  if (k < ncol - 1)
+    dw[(long)co * (ncol - 1) + k] = (float)s;
+  else if (db)
+    db[co] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_relu_grad(const float* __restrict__ y, float* __restrict__ g, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(y[i] > 0.f)) g[i] = 0.f;
+}
+
+// Adam: m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2; w -= lr mhat / (sqrt(vhat) + eps)
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, long n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int nchunks(long rows) { return (int)(rows < kChunks ? rows : kChunks); }
+
+pat_status conv_args(const char* who, int nb, int cin, int cout, int nz, int ny, int nx) {
+  if (nb < 0 || cin < 1 || cout < 1 || nz < 1 || ny < 1 || nx < 1)
+    return pat::set_error(PAT_ERR_INVALID, "%s: sizes must be positive (batch >= 0)", who);
+  if ((long)cin * kTaps > (1L << 20) || (long)cout > (1L << 16))
+    return pat::set_error(PAT_ERR_INVALID, "%s: too many channels", who);
+  if ((long)nb * cin * nz * ny * nx > (1L << 34) || (long)nb * cout * nz * ny * nx > (1L << 34))
+    return pat::set_error(PAT_ERR_INVALID, "%s: tensor too large", who);
+  return PAT_OK;
+}
+
+pat_status launched(const char* who) {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PAT_OK : pat::set_error(PAT_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
+}
+
+template <bool TW>
+pat_status launch_conv(const char* who, const float* x, const float* w, const float* bias, float* y, int nb, int cin,
+                       int cout, int nz, int ny, int nx, int relu, void* stream) {
+  if (nb == 0) return PAT_OK;
+  const int xtiles = (nx + 15) / 16, ctiles = (cout + 15) / 16;
+  const long waves = (long)nb * nz * ny * ctiles * xtiles;
+  const long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
+  hipLaunchKernelGGL(k_conv3d<TW>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, x, w,
+                     bias, y, nb, cin, cout, nz, ny, nx, relu, xtiles, ctiles);
+  return launched(who);
+}
+
+}  // namespace
+
+extern "C" {
+
+pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias, float* y, int32_t batch,
+                              int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
+                              void* stream) {
+  PAT_NN_CHECK(conv_args("pat_conv3d_forward", batch, c_in, c_out, nz, ny, nx));
+  if (batch > 0 && (!x || !w || !y)) return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_forward: null pointer");
+  return launch_conv<false>("pat_conv3d_forward", x, w, bias, y, batch, c_in, c_out, nz, ny, nx, relu ? 1 : 0, stream);
+}
+
+pat_status pat_conv3d_backward_input(const float* dy, const float* w, float* dx, int32_t batch, int32_t c_in,
+                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* stream) {
+  PAT_NN_CHECK(conv_args("pat_conv3d_backward_input", batch, c_in, c_out, nz, ny, nx));
+  if (batch > 0 && (!dy || !w || !dx))
+    return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_backward_input: null pointer");
+  // the forward over c_out input channels producing c_in, weights read transposed
+  return launch_conv<true>("pat_conv3d_backward_input", dy, w, nullptr, dx, batch, c_out, c_in, nz, ny, nx, 0,
+                           stream);
+}
+
+size_t pat_conv3d_backward_weight_workspace_bytes(int32_t batch, int32_t c_in, int32_t c_out, int32_t nz, int32_t ny,
+                                                  int32_t nx) {
+  if (conv_args("pat_conv3d_backward_weight_workspace_bytes", batch, c_in, c_out, nz, ny, nx) != PAT_OK) return 0;
+  const long rows = (long)batch * nz * ny;
+  const int nc = nchunks(rows < 1 ? 1 : rows);
+  return (size_t)nc * c_out * (c_in * kTaps + 1) * sizeof(float);
+}
+
+pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw, float* dbias, int32_t batch,
+                                      int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  PAT_NN_CHECK(conv_args("pat_conv3d_backward_weight", batch, c_in, c_out, nz, ny, nx));
+  if (!dw || (batch > 0 && (!x || !dy)))
+    return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_backward_weight: null pointer");
+  const size_t need = pat_conv3d_backward_weight_workspace_bytes(batch, c_in, c_out, nz, ny, nx);
+  if (!workspace || workspace_bytes < need)
+    return pat::set_error(PAT_ERR_NOMEM, "pat_conv3d_backward_weight: workspace of %zu bytes needed", need);
+  const long rows = (long)batch * nz * ny;
+  const int nc = nchunks(rows < 1 ? 1 : rows);
+  const int mtiles = (c_out + 15) / 16, ntiles = (c_in * kTaps + 1 + 15) / 16;
+  float* part = (float*)workspace;
+  if (rows > 0) {
+    const long waves = (long)nc * mtiles * ntiles;
+    hipLaunchKernelGGL(k_conv3d_wgrad_partial, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
+                       dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, x, dy, part, batch, c_in, c_out, nz, ny, nx,
+                       nc, mtiles, ntiles);
+    PAT_NN_CHECK(launched("pat_conv3d_backward_weight"));
+  }
+  const long n = (long)c_out * (c_in * kTaps + 1);
+  // with no rows every partial is zero: reduce over zero chunks
+  hipLaunchKernelGGL(k_conv3d_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     part, dw, dbias, c_in, c_out, rows > 0 ? nc : 0);
+  return launched("pat_conv3d_backward_weight");
+}
+
+pat_status pat_relu_backward(const float* y, float* grad, int64_t n, void* stream) {
+  if (n < 0) return pat::set_error(PAT_ERR_INVALID, "pat_relu_backward: n must be >= 0");
+  if (n == 0) return PAT_OK;
+  if (!y || !grad) return pat::set_error(PAT_ERR_INVALID, "pat_relu_backward: null pointer");
+  hipLaunchKernelGGL(k_relu_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, y, grad, n);
+  return launched("pat_relu_backward");
+}
+
+pat_status pat_adam_step(float* w, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int32_t step, void* stream) {
+  if (n < 0 || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return pat::set_error(PAT_ERR_INVALID, "pat_adam_step: argument out of range");
+  if (n == 0) return PAT_OK;
+  if (!w || !grad || !m || !v) return pat::set_error(PAT_ERR_INVALID, "pat_adam_step: null pointer");
+  const double c1 = 1.0 - std::pow((double)beta1, step), c2 = 1.0 - std::pow((double)beta2, step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w, grad, m, v, n,
+                     lr, beta1, beta2, eps, (float)c1, (float)c2);
+  return launched("pat_adam_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+"""Network layers of a learned update step (not part of the paper's method).
+
+Binding of include/pat_nn.h: 3x3x3 convolutions with BF16 operands on the
+matrix cores and FP32 accumulation, their input and weight gradients, the ReLU
+backward and an Adam step, all computed by libpat's kernels. This module checks
+tensors, passes pointers and the current stream, and wraps the convolution as a
+torch autograd function.
+"""
+
+import ctypes as C
+
+import torch
+
+from . import pat as P
+
+_P = C.c_void_p
+_I = C.c_int32
+SIGNATURES = {
+    "pat_conv3d_forward": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _I, _P]),
+    "pat_conv3d_backward_input": (C.c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _I, _P]),
+    "pat_conv3d_backward_weight_workspace_bytes": (C.c_size_t, [_I, _I, _I, _I, _I, _I]),
+    "pat_conv3d_backward_weight": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
+    "pat_relu_backward": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "pat_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, _P]),
+}
+
+_bound = False
+
+
+def lib():
+    global _bound
+    L = P.lib()
+    if not _bound:
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _bound = True
+    return L
+
+
+def _ptr(t, name, shape=None, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32 or t.device.type != "cuda" or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _sizes(x, w):
+    if x.dim() != 5 or w.dim() != 5 or tuple(w.shape[2:]) != (3, 3, 3):
+        raise ValueError("x must be [B, C, nz, ny, nx] and w [c_out, c_in, 3, 3, 3]")
+    if x.shape[1] != w.shape[1]:
+        raise ValueError(f"x has {x.shape[1]} channels, w expects {w.shape[1]}")
+    return (int(x.shape[0]), int(w.shape[1]), int(w.shape[0])) + tuple(int(s) for s in x.shape[2:])
+
+
+def conv3d_forward(x, w, bias=None, relu=False):
+    """y = conv(x, w) + bias, optionally ReLU; returns a new [B, c_out, nz, ny, nx] tensor."""
+    nb, ci, co, nz, ny, nx = _sizes(x, w)
+    y = torch.empty((nb, co, nz, ny, nx), dtype=torch.float32, device=x.device)
+    bp = None if bias is None else _ptr(bias, "bias", (co,), x.device)
+    P._check(lib().pat_conv3d_forward(_ptr(x, "x"), _ptr(w, "w", device=x.device), bp, _ptr(y, "y"), nb, ci, co,
+                                      nz, ny, nx, 1 if relu else 0, _stream(x)))
+    return y
+
+
+def conv3d_backward_input(dy, w):
+    """dx = the adjoint of x -> conv(x, w) applied to dy."""
+    nb, co = int(dy.shape[0]), int(w.shape[0])
+    if dy.dim() != 5 or dy.shape[1] != co:
+        raise ValueError("dy must be [B, c_out, nz, ny, nx]")
+    ci = int(w.shape[1])
+    nz, ny, nx = (int(s) for s in dy.shape[2:])
+    dx = torch.empty((nb, ci, nz, ny, nx), dtype=torch.float32, device=dy.device)
+    P._check(lib().pat_conv3d_backward_input(_ptr(dy, "dy"), _ptr(w, "w", device=dy.device), _ptr(dx, "dx"), nb, ci,
+                                             co, nz, ny, nx, _stream(dy)))
+    return dx
+
+
+def conv3d_backward_weight(x, dy, c_out=None):
+    """(dw, dbias): gradients of sum(dy * conv(x, w)) with respect to w and the bias."""
+    nb, ci = int(x.shape[0]), int(x.shape[1])
+    co = int(dy.shape[1]) if c_out is None else int(c_out)
+    nz, ny, nx = (int(s) for s in x.shape[2:])
+    _ptr(dy, "dy", (nb, co, nz, ny, nx), x.device)
+    nbytes = lib().pat_conv3d_backward_weight_workspace_bytes(nb, ci, co, nz, ny, nx)
+    if nbytes == 0:
+        raise ValueError("invalid convolution sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    dw = torch.empty((co, ci, 3, 3, 3), dtype=torch.float32, device=x.device)
+    db = torch.empty((co,), dtype=torch.float32, device=x.device)
+    P._check(lib().pat_conv3d_backward_weight(_ptr(x, "x"), _ptr(dy, "dy"), _ptr(dw, "dw"), _ptr(db, "db"), nb, ci,
+                                              co, nz, ny, nx, C.c_void_p(ws.data_ptr()), nbytes, _stream(x)))
+    return dw, db
+
+
+def relu_backward_(y, g):
+    """g[y <= 0] = 0 in place."""
+    if y.shape != g.shape:
+        raise ValueError("y and g must have the same shape")
+    P._check(lib().pat_relu_backward(_ptr(y, "y"), _ptr(g, "g", device=y.device), y.numel(), _stream(y)))
+    return g
+
+
+def adam_step_(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on w, m, v (step counts from 1)."""
+    for t, n in ((g, "g"), (m, "m"), (v, "v")):
+        _ptr(t, n, w.shape, w.device)
+    P._check(lib().pat_adam_step(_ptr(w, "w"), _ptr(g, "g"), _ptr(m, "m"), _ptr(v, "v"), w.numel(), float(lr),
+                                 float(beta1), float(beta2), float(eps), int(step), _stream(w)))
+
+
+class _Conv3d(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, w, bias, relu):
+        x, w = x.detach().contiguous(), w.detach().contiguous()
+        y = conv3d_forward(x, w, None if bias is None else bias.detach().contiguous(), relu)
+        ctx.relu, ctx.has_bias = relu, bias is not None
+        ctx.save_for_backward(x, w, y)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w, y = ctx.saved_tensors
+        g = gy.contiguous().clone() if ctx.relu else gy.contiguous()
+        if ctx.relu:
+            relu_backward_(y, g)
+        dx = conv3d_backward_input(g, w) if ctx.needs_input_grad[0] else None
+        dw, db = conv3d_backward_weight(x, g, w.shape[0]) if (ctx.needs_input_grad[1] or ctx.needs_input_grad[2]) \
+            else (None, None)
+        return dx, dw, db if ctx.has_bias else None, None
+
+
+def conv3d(x, w, bias=None, relu=False):
+    """Differentiable BF16-MFMA convolution (3x3x3, zero padding 1) with optional ReLU."""
+    return _Conv3d.apply(x, w, bias, relu)

@@ -12,10 +12,11 @@ from paper_1605_00133_amd import pat as P
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pat.h")
+NN_HEADER = os.path.join(ROOT, "include", "pat_nn.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(pat_[a-z0-9_]+)\s*\(", text)))
 
@@ -27,6 +28,32 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), f"{n} declared in include/pat.h but not exported"
     assert set(names) == set(P.SIGNATURES), "binding and header disagree"
+
+
+def test_library_exports_every_nn_function():
+    from paper_1605_00133_amd import nn
+    lib = nn.lib()
+    names = declared_functions(NN_HEADER)
+    assert len(names) == 6
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/pat_nn.h but not exported"
+    assert set(names) == set(nn.SIGNATURES), "nn binding and header disagree"
+
+
+def test_nn_validation_without_gpu():
+    from paper_1605_00133_amd import nn
+    lib = nn.lib()
+    # K = 27 * 3 + 1 bias column, 2 * 5 * 6 = 60 rows -> 60 chunks
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(2, 3, 20, 5, 6, 37) == 60 * 20 * 82 * 4
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 16, 16, 128, 128, 128) == 256 * 16 * 433 * 4
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(1, 0, 16, 8, 8, 8) == 0
+    assert lib.pat_conv3d_forward(None, None, None, None, 1, 0, 4, 8, 8, 8, 0, None) == 1
+    assert b"sizes must be positive" in P.lib().pat_last_error()
+    assert lib.pat_conv3d_forward(None, None, None, None, 1, 2, 4, 8, 8, 8, 0, None) == 1
+    assert b"null pointer" in P.lib().pat_last_error()
+    assert lib.pat_conv3d_forward(None, None, None, None, 0, 2, 4, 8, 8, 8, 0, None) == 0   # empty batch
+    assert lib.pat_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == 1
+    assert lib.pat_relu_backward(None, None, -1, None) == 1
 
 
 def test_version_string():

@@ -36,17 +36,25 @@
 extern "C" {
 #endif
 
+/* Bytes of device workspace pat_conv3d_forward and pat_conv3d_backward_input
+ * need for a layer with these channel counts (0 for invalid counts): the
+ * weights repacked as bfloat16 matrix-core operands. */
+size_t pat_conv3d_workspace_bytes(int32_t c_in, int32_t c_out);
+
 /* y = conv(x, w) + bias (bias may be NULL), then max(y, 0) if relu != 0.
- * x [batch][c_in][nz][ny][nx], y [batch][c_out][nz][ny][nx]; x and y must not overlap. */
+ * x [batch][c_in][nz][ny][nx], y [batch][c_out][nz][ny][nx]; x and y must not
+ * overlap. workspace: device scratch of at least pat_conv3d_workspace_bytes. */
 pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias, float* y, int32_t batch,
                               int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
-                              void* stream);
+                              void* workspace, size_t workspace_bytes, void* stream);
 
 /* dx = gradient of sum(dy * conv(x, w)) with respect to x: the adjoint of the
  * convolution (weights transposed over channels, taps mirrored).
- * dy [batch][c_out][...], dx [batch][c_in][...] (overwritten); no overlap. */
+ * dy [batch][c_out][...], dx [batch][c_in][...] (overwritten); no overlap.
+ * workspace as for pat_conv3d_forward. */
 pat_status pat_conv3d_backward_input(const float* dy, const float* w, float* dx, int32_t batch, int32_t c_in,
-                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* stream);
+                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* workspace,
+                                     size_t workspace_bytes, void* stream);
 
 /* Bytes of device workspace pat_conv3d_backward_weight needs for these sizes
  * (0 for invalid sizes). */

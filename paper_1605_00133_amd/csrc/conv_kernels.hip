@@ -114,6 +114,114 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d(
   }
 }
 
+// Packed weights: the B operand of every 16-wide K chunk in lane order,
+// wb[((ct * nch + ch) * 64 + lane) * 4 + i] = B[k = 16 ch + 4 q + i][n = 16 ct + r],
+// K ordered tap-major over a channel count padded to a multiple of 4
+// (k = tap * cpad + c), zero outside the layer. TW: the input-gradient form.
+template <bool TW>
+__global__ __launch_bounds__(256) void k_conv3d_pack_weights(const float* __restrict__ w, short* __restrict__ wb,
+                                                             int cin, int cout, int cpad, int nch, int ctiles) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)ctiles * nch * 256) return;
+  const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
+  const long cc = i >> 8;
+  const int ch = (int)(cc % nch), ct = (int)(cc / nch);
+  const int k = ch * 16 + 4 * (lane >> 4) + e, n = ct * 16 + (lane & 15);
+  float v = 0.f;
+  if (k < kTaps * cpad && n < cout) {
+    const int tap = k / cpad, c = k - tap * cpad;
+    if (c < cin)
+      v = TW ? w[((long)c * cout + n) * kTaps + (kTaps - 1 - tap)] : w[((long)n * cin + c) * kTaps + tap];
+  }
+  wb[i] = bf16_rne(v);
+}
+
+constexpr int kTileX = 16, kTileY = 4;                     // output tile of one block: one row per wave
+constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2;
+constexpr int kMaxCpadLds = 64;                            // larger layers use k_conv3d
+constexpr int kMaxCt = 4;                                  // output-channel tiles per block
+
+// The input halo of a 16 x 4 x 1 output tile sits in LDS as bfloat16, channels
+// innermost ([dz][y][x][cpad]): the A operand of a lane (4 channels at one tap
+// of its voxel) is one 8-byte LDS read. The packed B operand is one 8-byte
+// global read per lane, the same for every block (cache-resident).
+__global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x, const short* __restrict__ wb,
+                                                    const float* __restrict__ bias, float* __restrict__ y, int nb,
+                                                    int cin, int cout, int nz, int ny, int nx, int relu, int cpad,
+                                                    int nch, int ctiles, int xtiles, int ytiles, int cgroups) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  short* xs = reinterpret_cast<short*>(smem);
+  const int halo = 3 * kHaloY * kHaloX * cpad;
+  int* qoff = reinterpret_cast<int*>(xs + halo);           // halo is a multiple of 4 elements
+  const int nq = kTaps * cpad / 4;
+  long t = blockIdx.x;
+  const int xt = (int)(t % xtiles);
+  t /= xtiles;
+  const int yt = (int)(t % ytiles);
+  t /= ytiles;
+  const int cg = (int)(t % cgroups);
+  t /= cgroups;
+  const int zz = (int)(t % nz);
+  const int b = (int)(t / nz);
+  const int x0 = xt * kTileX, y0 = yt * kTileY;
+  const int tid = threadIdx.x;
+  for (int j = tid; j < nq; j += 256) {
+    const int tap = j / (cpad / 4), cq = j - tap * (cpad / 4);
+    qoff[j] = (((tap / 9) * kHaloY + (tap / 3) % 3) * kHaloX + tap % 3) * cpad + 4 * cq;
+  }
+  const long vol = (long)nz * ny * nx;
+  const float* xb = x + (long)b * cin * vol;
+  for (int i = tid; i < halo; i += 256) {                  // x fastest: coalesced global reads
+    const int hx = i % kHaloX;
+    int rest = i / kHaloX;
+    const int hy = rest % kHaloY;
+    rest /= kHaloY;
+    const int hz = rest % 3, c = rest / 3;
+    const int gz = zz + hz - 1, gy = y0 + hy - 1, gx = x0 + hx - 1;
+    float v = 0.f;
+    if (c < cin && gz >= 0 && gz < nz && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+      v = xb[c * vol + ((long)gz * ny + gy) * nx + gx];
+    xs[((hz * kHaloY + hy) * kHaloX + hx) * cpad + c] = bf16_rne(v);
+  }
+  __syncthreads();
+  const int lane = tid & 63, wy = tid >> 6, r = lane & 15, q = lane >> 4;
+  const int ct0 = cg * kMaxCt, nct = min(kMaxCt, ctiles - ct0);
+  const short* arow = xs + (wy * kHaloX + r) * cpad;
+  f32x4 acc[kMaxCt];
+#pragma unroll
+  for (int c = 0; c < kMaxCt; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x4 zero = {0, 0, 0, 0};
+  for (int ch = 0; ch < nch; ++ch) {
+    const int j = ch * 4 + q;
+    const bf16x4 a = j < nq ? *reinterpret_cast<const bf16x4*>(arow + qoff[j]) : zero;
+#pragma unroll
+    for (int c = 0; c < kMaxCt; ++c) {
+      if (c < nct) {
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(wb + (((long)(ct0 + c) * nch + ch) * 64 + lane) * 4);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[c], 0, 0, 0);
+      }
+    }
+  }
+  const int yo = y0 + wy;
+  if (yo >= ny) return;
+#pragma unroll
+  for (int c = 0; c < kMaxCt; ++c) {
+    const int co = (ct0 + c) * 16 + r;
+    if (c < nct && co < cout) {
+      const float bb = bias ? bias[co] : 0.f;
+      float* yrow = y + ((long)b * cout + co) * vol + ((long)zz * ny + yo) * nx;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int xo = x0 + 4 * q + i;
+        if (xo < nx) {
+          const float v = acc[c][i] + bb;
+          yrow[xo] = relu ? fmaxf(v, 0.f) : v;
+        }
+      }
+    }
+  }
+}
+
 // Weight (and bias) gradient partials: GEMM with M = co, N = k (27 cin taps, then one
 // column of ones for the bias), K = voxels. Wave (chunk, mt, nt) sums the rows
 // chunk, chunk + nchunk, ... of the B * nz * ny rows, 16 x positions at a time.
@@ -230,16 +338,43 @@ pat_status launched(const char* who) {
   return e == hipSuccess ? PAT_OK : pat::set_error(PAT_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
 }
 
+int conv_cpad(int cin) { return (cin + 3) / 4 * 4; }
+int conv_nch(int cin) { return (kTaps * conv_cpad(cin) + 15) / 16; }
+bool conv_uses_lds(int cin) { return conv_cpad(cin) <= kMaxCpadLds; }
+size_t conv_pack_bytes(int cin, int cout) {
+  return conv_uses_lds(cin) ? (size_t)((cout + 15) / 16) * conv_nch(cin) * 256 * sizeof(short) : 0;
+}
+
 template <bool TW>
 pat_status launch_conv(const char* who, const float* x, const float* w, const float* bias, float* y, int nb, int cin,
-                       int cout, int nz, int ny, int nx, int relu, void* stream) {
+                       int cout, int nz, int ny, int nx, int relu, void* workspace, size_t workspace_bytes,
+                       void* stream) {
   if (nb == 0) return PAT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (conv_uses_lds(cin)) {
+    const size_t need = conv_pack_bytes(cin, cout);
+    if (!workspace || workspace_bytes < need)
+      return pat::set_error(PAT_ERR_NOMEM, "%s: workspace of %zu bytes needed", who, need);
+    const int cpad = conv_cpad(cin), nch = conv_nch(cin), ctiles = (cout + 15) / 16;
+    short* wb = (short*)workspace;
+    const long npack = (long)ctiles * nch * 256;
+    hipLaunchKernelGGL(k_conv3d_pack_weights<TW>, dim3((unsigned)((npack + 255) / 256)), dim3(256), 0, st, w, wb, cin,
+                       cout, cpad, nch, ctiles);
+    const int xtiles = (nx + kTileX - 1) / kTileX, ytiles = (ny + kTileY - 1) / kTileY;
+    const int cgroups = (ctiles + kMaxCt - 1) / kMaxCt;
+    const long blocks = (long)nb * nz * cgroups * ytiles * xtiles;
+    if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
+    const size_t lds = (size_t)3 * kHaloY * kHaloX * cpad * sizeof(short) + (size_t)(kTaps * cpad / 4) * sizeof(int);
+    hipLaunchKernelGGL(k_conv3d_lds, dim3((unsigned)blocks), dim3(256), lds, st, x, wb, bias, y, nb, cin, cout, nz, ny,
+                       nx, relu, cpad, nch, ctiles, xtiles, ytiles, cgroups);
+    return launched(who);
+  }
   const int xtiles = (nx + 15) / 16, ctiles = (cout + 15) / 16;
   const long waves = (long)nb * nz * ny * ctiles * xtiles;
   const long blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
-  hipLaunchKernelGGL(k_conv3d<TW>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, x, w,
-                     bias, y, nb, cin, cout, nz, ny, nx, relu, xtiles, ctiles);
+  hipLaunchKernelGGL(k_conv3d<TW>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st, x, w, bias, y, nb, cin,
+                     cout, nz, ny, nx, relu, xtiles, ctiles);
   return launched(who);
 }
 
@@ -247,22 +382,32 @@ pat_status launch_conv(const char* who, const float* x, const float* w, const fl
 
 extern "C" {
 
+size_t pat_conv3d_workspace_bytes(int32_t c_in, int32_t c_out) {
+  if (c_in < 1 || c_out < 1 || (long)c_in * kTaps > (1L << 20) || (long)c_out > (1L << 16)) return 0;
+  // forward packs (c_in -> c_out), the input gradient (c_out -> c_in): room for either
+  const size_t a = conv_pack_bytes(c_in, c_out), b = conv_pack_bytes(c_out, c_in);
+  const size_t m = a > b ? a : b;
+  return m > 0 ? m : 256;
+}
+
 pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias, float* y, int32_t batch,
                               int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
-                              void* stream) {
+                              void* workspace, size_t workspace_bytes, void* stream) {
   PAT_NN_CHECK(conv_args("pat_conv3d_forward", batch, c_in, c_out, nz, ny, nx));
   if (batch > 0 && (!x || !w || !y)) return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_forward: null pointer");
-  return launch_conv<false>("pat_conv3d_forward", x, w, bias, y, batch, c_in, c_out, nz, ny, nx, relu ? 1 : 0, stream);
+  return launch_conv<false>("pat_conv3d_forward", x, w, bias, y, batch, c_in, c_out, nz, ny, nx, relu ? 1 : 0,
+                            workspace, workspace_bytes, stream);
 }
 
 pat_status pat_conv3d_backward_input(const float* dy, const float* w, float* dx, int32_t batch, int32_t c_in,
-                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* stream) {
+                                     int32_t c_out, int32_t nz, int32_t ny, int32_t nx, void* workspace,
+                                     size_t workspace_bytes, void* stream) {
   PAT_NN_CHECK(conv_args("pat_conv3d_backward_input", batch, c_in, c_out, nz, ny, nx));
   if (batch > 0 && (!dy || !w || !dx))
     return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_backward_input: null pointer");
   // the forward over c_out input channels producing c_in, weights read transposed
   return launch_conv<true>("pat_conv3d_backward_input", dy, w, nullptr, dx, batch, c_out, c_in, nz, ny, nx, 0,
-                           stream);
+                           workspace, workspace_bytes, stream);
 }
 
 size_t pat_conv3d_backward_weight_workspace_bytes(int32_t batch, int32_t c_in, int32_t c_out, int32_t nz, int32_t ny,

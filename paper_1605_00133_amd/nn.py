@@ -16,8 +16,9 @@ from . import pat as P
 _P = C.c_void_p
 _I = C.c_int32
 SIGNATURES = {
-    "pat_conv3d_forward": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _I, _P]),
-    "pat_conv3d_backward_input": (C.c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _I, _P]),
+    "pat_conv3d_workspace_bytes": (C.c_size_t, [_I, _I]),
+    "pat_conv3d_forward": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
+    "pat_conv3d_backward_input": (C.c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
     "pat_conv3d_backward_weight_workspace_bytes": (C.c_size_t, [_I, _I, _I, _I, _I, _I]),
     "pat_conv3d_backward_weight": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
     "pat_relu_backward": (C.c_int, [_P, _P, C.c_int64, _P]),
@@ -63,13 +64,21 @@ def _sizes(x, w):
     return (int(x.shape[0]), int(w.shape[1]), int(w.shape[0])) + tuple(int(s) for s in x.shape[2:])
 
 
+def _workspace(ci, co, device):
+    nbytes = lib().pat_conv3d_workspace_bytes(ci, co)
+    if nbytes == 0:
+        raise ValueError("invalid channel counts")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
 def conv3d_forward(x, w, bias=None, relu=False):
     """y = conv(x, w) + bias, optionally ReLU; returns a new [B, c_out, nz, ny, nx] tensor."""
     nb, ci, co, nz, ny, nx = _sizes(x, w)
     y = torch.empty((nb, co, nz, ny, nx), dtype=torch.float32, device=x.device)
     bp = None if bias is None else _ptr(bias, "bias", (co,), x.device)
+    ws, nbytes = _workspace(ci, co, x.device)
     P._check(lib().pat_conv3d_forward(_ptr(x, "x"), _ptr(w, "w", device=x.device), bp, _ptr(y, "y"), nb, ci, co,
-                                      nz, ny, nx, 1 if relu else 0, _stream(x)))
+                                      nz, ny, nx, 1 if relu else 0, C.c_void_p(ws.data_ptr()), nbytes, _stream(x)))
     return y
 
 
@@ -81,8 +90,9 @@ def conv3d_backward_input(dy, w):
     ci = int(w.shape[1])
     nz, ny, nx = (int(s) for s in dy.shape[2:])
     dx = torch.empty((nb, ci, nz, ny, nx), dtype=torch.float32, device=dy.device)
+    ws, nbytes = _workspace(ci, co, dy.device)
     P._check(lib().pat_conv3d_backward_input(_ptr(dy, "dy"), _ptr(w, "w", device=dy.device), _ptr(dx, "dx"), nb, ci,
-                                             co, nz, ny, nx, _stream(dy)))
+                                             co, nz, ny, nx, C.c_void_p(ws.data_ptr()), nbytes, _stream(dy)))
     return dx
 
 

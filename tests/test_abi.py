@@ -34,7 +34,7 @@ def test_library_exports_every_nn_function():
     from paper_1605_00133_amd import nn
     lib = nn.lib()
     names = declared_functions(NN_HEADER)
-    assert len(names) == 6
+    assert len(names) == 7
     for n in names:
         assert hasattr(lib, n), f"{n} declared in include/pat_nn.h but not exported"
     assert set(names) == set(nn.SIGNATURES), "nn binding and header disagree"
@@ -47,11 +47,16 @@ def test_nn_validation_without_gpu():
     assert lib.pat_conv3d_backward_weight_workspace_bytes(2, 3, 20, 5, 6, 37) == 60 * 20 * 82 * 4
     assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 16, 16, 128, 128, 128) == 256 * 16 * 433 * 4
     assert lib.pat_conv3d_backward_weight_workspace_bytes(1, 0, 16, 8, 8, 8) == 0
-    assert lib.pat_conv3d_forward(None, None, None, None, 1, 0, 4, 8, 8, 8, 0, None) == 1
+    # packed weights: ceil(co / 16) tiles x ceil(27 cpad / 16) chunks x 256 bfloat16, cpad = ci rounded up to 4
+    assert lib.pat_conv3d_workspace_bytes(3, 20) == max(2 * 7 * 512, 1 * 34 * 512)
+    assert lib.pat_conv3d_workspace_bytes(24, 24) == 2 * 41 * 512
+    assert lib.pat_conv3d_workspace_bytes(70, 70) == 256          # both directions use the unpacked kernel
+    assert lib.pat_conv3d_workspace_bytes(0, 4) == 0
+    assert lib.pat_conv3d_forward(None, None, None, None, 1, 0, 4, 8, 8, 8, 0, None, 0, None) == 1
     assert b"sizes must be positive" in P.lib().pat_last_error()
-    assert lib.pat_conv3d_forward(None, None, None, None, 1, 2, 4, 8, 8, 8, 0, None) == 1
+    assert lib.pat_conv3d_forward(None, None, None, None, 1, 2, 4, 8, 8, 8, 0, None, 0, None) == 1
     assert b"null pointer" in P.lib().pat_last_error()
-    assert lib.pat_conv3d_forward(None, None, None, None, 0, 2, 4, 8, 8, 8, 0, None) == 0   # empty batch
+    assert lib.pat_conv3d_forward(None, None, None, None, 0, 2, 4, 8, 8, 8, 0, None, 0, None) == 0   # empty batch
     assert lib.pat_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == 1
     assert lib.pat_relu_backward(None, None, -1, None) == 1
 

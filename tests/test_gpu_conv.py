@@ -6,8 +6,11 @@ takes the same bfloat16-rounded operands and sums in FP64. Products of two
 bfloat16 values are exact in FP32, so the two differ only by FP32 summation:
 relative L2 below 1e-5 for every layer (sums of at most 27 * 16 = 432 terms,
 or chunked FP32 sums of a few hundred terms added in FP64 for the weights).
-Sizes are ragged against the 16 x 16 tiles (x extent 37, 20 output channels,
-K = 27 * 3 = 81) as well as the shapes of the learned update network.
+Sizes are ragged against the 16 x 16 tiles and the 16 x 4 output tiles of a
+block (x extent 37, y extent 7, 20 output channels, K = 27 * 3 = 81), cover
+both forward kernels (packed operands with the input halo in LDS for up to 64
+padded input channels, the unpacked kernel above) and the shapes of the
+learned update network.
 """
 
 import numpy as np
@@ -24,6 +27,9 @@ CASES = [  # (batch, c_in, c_out, nz, ny, nx)
     (1, 2, 16, 32, 32, 32),
     (2, 16, 1, 8, 9, 10),
     (1, 1, 1, 1, 1, 1),
+    (1, 24, 24, 6, 7, 33),
+    (1, 70, 5, 4, 5, 18),      # forward on the unpacked kernel (more than 64 input channels)
+    (1, 5, 70, 3, 4, 17),      # five output-channel tiles: two channel groups per tile
 ]
 
 

@@ -222,16 +222,19 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   }
 }
 
+constexpr int kWgCols = 4;   // most column tiles per wave of the weight gradient (they share the dy operand)
+
 // Weight (and bias) gradient partials: GEMM with M = co, N = k (27 cin taps, then one
-// column of ones for the bias), K = voxels. Wave (chunk, mt, nt) sums the rows
-// chunk, chunk + nchunk, ... of the B * nz * ny rows, 16 x positions at a time.
+// column of ones for the bias), K = voxels. Wave (chunk, mt, column group) sums the
+// rows chunk, chunk + nchunk, ... of the B * nz * ny rows, 16 x positions at a time,
+// into ncw <= kWgCols column tiles that share one A operand (dy).
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d_wgrad_partial(
     const float* __restrict__ x, const float* __restrict__ gy, float* __restrict__ part, int nb, int cin,
-    int cout, int nz, int ny, int nx, int nchunk, int mtiles, int ntiles) {
+    int cout, int nz, int ny, int nx, int nchunk, int mtiles, int ngroups, int ncw) {
   const int lane = threadIdx.x & 63;
   long t = (long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int nt = (int)(t % ntiles);
-  t /= ntiles;
+  const int ng = (int)(t % ngroups);
+  t /= ngroups;
   const int mt = (int)(t % mtiles);
   t /= mtiles;
   const int chunk = (int)t;
@@ -241,49 +244,70 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d_wgrad_partial(
   const long vol = (long)nz * ny * nx;
   const long rows = (long)nb * nz * ny;
   const int co_a = mt * 16 + r;   // A row of this lane
-  const int kb = nt * 16 + r;     // B column of this lane
-  int ci = 0, dz = 0, dy = 0, dx = 0;
-  const bool wcol = kb < ncol - 1, bcol = kb == ncol - 1;
-  if (wcol) {
-    ci = kb / kTaps;
-    tap_offset(kb - ci * kTaps, dz, dy, dx);
+  int ci[kWgCols], dz[kWgCols], dyo[kWgCols], dx[kWgCols];
+  bool wcol[kWgCols], bcol[kWgCols];
+#pragma unroll
+  for (int j = 0; j < kWgCols; ++j) {
+    const int kb = j < ncw ? (ng * ncw + j) * 16 + r : ncol;   // B column of this lane in tile j
+    wcol[j] = kb < ncol - 1;
+    bcol[j] = kb == ncol - 1;
+    ci[j] = wcol[j] ? kb / kTaps : 0;
+    tap_offset(wcol[j] ? kb - ci[j] * kTaps : 13, dz[j], dyo[j], dx[j]);
   }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[kWgCols];
+#pragma unroll
+  for (int j = 0; j < kWgCols; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (long row = chunk; row < rows; row += nchunk) {
     const int yy = (int)(row % ny);
     const int zz = (int)((row / ny) % nz);
     const int b = (int)(row / ((long)ny * nz));
     const float* dyrow = gy + ((long)b * cout + co_a) * vol + ((long)zz * ny + yy) * nx;
-    const int z2 = zz + dz, y2 = yy + dy;
-    const bool rowin = wcol && z2 >= 0 && z2 < nz && y2 >= 0 && y2 < ny;
-    const float* xrow = x + ((long)b * cin + ci) * vol + ((long)(rowin ? z2 : 0) * ny + (rowin ? y2 : 0)) * nx;
+    const float* xrow[kWgCols];
+    bool rowin[kWgCols];
+#pragma unroll
+    for (int j = 0; j < kWgCols; ++j) {
+      const int z2 = zz + dz[j], y2 = yy + dyo[j];
+      rowin[j] = wcol[j] && z2 >= 0 && z2 < nz && y2 >= 0 && y2 < ny;
+      xrow[j] = x + ((long)b * cin + ci[j]) * vol + ((long)(rowin[j] ? z2 : 0) * ny + (rowin[j] ? y2 : 0)) * nx;
+    }
     for (int x0 = 0; x0 < nx; x0 += 16) {
-      bf16x4 a, bv;
+      bf16x4 a;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int xv = x0 + 4 * q + i;
-        float av = 0.f, bx = 0.f;
-        if (xv < nx) {
-          if (co_a < cout) av = dyrow[xv];
-          if (rowin) {
-            const int x2 = xv + dx;
-            if (x2 >= 0 && x2 < nx) bx = xrow[x2];
-          } else if (bcol) {
-            bx = 1.f;
-          }
-        }
-        a[i] = bf16_rne(av);
-        bv[i] = bf16_rne(bx);
+        a[i] = bf16_rne(xv < nx && co_a < cout ? dyrow[xv] : 0.f);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < kWgCols; ++j) {
+        bf16x4 bv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int xv = x0 + 4 * q + i;
+          float bx = 0.f;
+          if (xv < nx) {
+            if (rowin[j]) {
+              const int x2 = xv + dx[j];
+              if (x2 >= 0 && x2 < nx) bx = xrow[j][x2];
+            } else if (bcol[j]) {
+              bx = 1.f;
+            }
+          }
+          bv[i] = bf16_rne(bx);
+        }
+        if (j < ncw) acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[j], 0, 0, 0);   // uniform
+      }
     }
   }
-  if (kb >= ncol) return;
   float* p = part + (long)chunk * cout * ncol;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int co = mt * 16 + 4 * q + i;
-    if (co < cout) p[(long)co * ncol + kb] = acc[i];
+  for (int j = 0; j < kWgCols; ++j) {
+    const int kb = (ng * ncw + j) * 16 + r;
+    if (j >= ncw || kb >= ncol) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = mt * 16 + 4 * q + i;
+      if (co < cout) p[(long)co * ncol + kb] = acc[j][i];
+    }
   }
 }
 
@@ -430,12 +454,15 @@ pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw
   const long rows = (long)batch * nz * ny;
   const int nc = nchunks(rows < 1 ? 1 : rows);
   const int mtiles = (c_out + 15) / 16, ntiles = (c_in * kTaps + 1 + 15) / 16;
+  // sharing dy pays when there are many column tiles; with few, one tile per wave keeps more waves
+  const int ncw = ntiles >= 16 ? kWgCols : 1;
+  const int ngroups = (ntiles + ncw - 1) / ncw;
   float* part = (float*)workspace;
   if (rows > 0) {
-    const long waves = (long)nc * mtiles * ntiles;
+    const long waves = (long)nc * mtiles * ngroups;
     hipLaunchKernelGGL(k_conv3d_wgrad_partial, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
                        dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, x, dy, part, batch, c_in, c_out, nz, ny, nx,
-                       nc, mtiles, ntiles);
+                       nc, mtiles, ngroups, ncw);
     PAT_NN_CHECK(launched("pat_conv3d_backward_weight"));
   }
   const long n = (long)c_out * (c_in * kTaps + 1);

@@ -311,19 +311,28 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d_wgrad_partial(
   }
 }
 
-// dw[co][k] = sum over chunks in order (FP64); the last column goes to db.
+// dw[co][k] = sum over the chunks (FP64, fixed order: 16 interleaved partial sums per
+// column, then those 16 in order); the last column goes to db. Block: 16 columns x 16.
 __global__ __launch_bounds__(256) void k_conv3d_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
                                                              float* __restrict__ db, int cin, int cout, int nchunk) {
+  __shared__ double red[16][17];
   const int ncol = cin * kTaps + 1;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)cout * ncol) return;
+  const long total = (long)cout * ncol;
+  const int lc = threadIdx.x & 15, lk = threadIdx.x >> 4;
+  const long i = (long)blockIdx.x * 16 + lc;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(long)c * cout * ncol + i];
+  if (i < total)
+    for (int c = lk; c < nchunk; c += 16) s += part[(long)c * total + i];
+  red[lk][lc] = s;
+  __syncthreads();
+  if (lk != 0 || i >= total) return;
+  double t = 0.0;
+  for (int j = 0; j < 16; ++j) t += red[j][lc];
   const int co = (int)(i / ncol), k = (int)(i % ncol);
   if (k < ncol - 1)
-    dw[(long)co * (ncol - 1) + k] = (float)s;
+    dw[(long)co * (ncol - 1) + k] = (float)t;
   else if (db)
-    db[co] = (float)s;
+    db[co] = (float)t;
 }
 
 __global__ __launch_bounds__(256) void k_relu_grad(const float* __restrict__ y, float* __restrict__ g, long n) {
@@ -467,7 +476,7 @@ pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw
   }
   const long n = (long)c_out * (c_in * kTaps + 1);
   // with no rows every partial is zero: reduce over zero chunks
-  hipLaunchKernelGGL(k_conv3d_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(k_conv3d_wgrad_reduce, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, (hipStream_t)stream,
                      part, dw, dbias, c_in, c_out, rows > 0 ? nc : 0);
   return launched("pat_conv3d_backward_weight");
 }

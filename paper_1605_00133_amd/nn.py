@@ -153,3 +153,42 @@ class _Conv3d(torch.autograd.Function):
 def conv3d(x, w, bias=None, relu=False):
     """Differentiable BF16-MFMA convolution (3x3x3, zero padding 1) with optional ReLU."""
     return _Conv3d.apply(x, w, bias, relu)
+
+
+def bench_layers(shapes=((8, 2, 24, 32), (8, 24, 24, 32), (8, 24, 1, 32), (1, 16, 16, 128)), reps=20):
+    """HIP-event timings (us per call) of forward, input gradient and weight gradient
+    for [batch, c_in, c_out, n^3] layers on random data; one host thread, one stream."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(0)
+    out = []
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    for nb, ci, co, n in shapes:
+        x = torch.randn((nb, ci, n, n, n), generator=g, device=dev)
+        w = torch.randn((co, ci, 3, 3, 3), generator=g, device=dev)
+        b = torch.randn((co,), generator=g, device=dev)
+        dy = torch.randn((nb, co, n, n, n), generator=g, device=dev)
+        flop = 2.0 * nb * n ** 3 * ci * co * 27
+        r = {"batch": nb, "c_in": ci, "c_out": co, "n": n,
+             "forward_us": timed(lambda: conv3d_forward(x, w, b, True)),
+             "input_grad_us": timed(lambda: conv3d_backward_input(dy, w)),
+             "weight_grad_us": timed(lambda: conv3d_backward_weight(x, dy))}
+        r["forward_tflops"] = flop / r["forward_us"] / 1e6
+        out.append(r)
+    return out
+
+
+if __name__ == "__main__":
+    import json
+    for r in bench_layers():
+        print(json.dumps({k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}), flush=True)

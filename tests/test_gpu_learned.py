@@ -14,3 +14,29 @@ def test_learned_update_beats_plain_fista_with_equal_pairs():
     print(out)
     assert out["train_mse"][-1] < out["train_mse"][0]
     assert out["psnr_db_learned_minus_plain"] > 1.0
+
+
+def test_captured_graph_replays_equal_eager():
+    """The learned iteration captured as one HIP graph: several replays on new data,
+    with eager work and synchronisations between them, each equal bit for bit to
+    the eager iteration on the same data."""
+    import numpy as np
+    import torch
+    from paper_1605_00133_amd import pat as P
+    from paper_1605_00133_amd.learned import CapturedReconstruct, LearnedUpdate, reconstruct
+    from gpu_cases import gaussian_data, gpu_plan, oracle_sampling, phantom, to_dev
+    n, nt = 32, 100
+    plan = gpu_plan(n, nt, oracle_sampling("points", n))
+    model = LearnedUpdate(n_steps=3, channels=8, seed=2)
+    L = 5.0
+    cap = CapturedReconstruct(model, plan, L)
+    for k in range(4):
+        f = torch.empty(plan.data_shape, device="cuda")
+        P.pat_forward(plan, to_dev(phantom(n, seed=10 + k)), f)
+        f += 0.01 * to_dev(gaussian_data(f.shape, 20 + k))
+        pg = cap(f).clone()
+        torch.cuda.synchronize()
+        pe = reconstruct(model, plan, f, L)          # eager, between replays
+        torch.cuda.synchronize()
+        assert torch.equal(pg, pe), f"replay {k} differs from the eager iteration"
+        assert float(pe.abs().sum()) > 0

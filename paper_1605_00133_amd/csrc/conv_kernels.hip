@@ -35,6 +35,8 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));   // bit patterns of 8 bfloat16
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTaps = 27;
@@ -114,19 +116,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d(
   }
 }
 
-// Packed weights: the B operand of every 16-wide K chunk in lane order,
-// wb[((ct * nch + ch) * 64 + lane) * 4 + i] = B[k = 16 ch + 4 q + i][n = 16 ct + r],
-// K ordered tap-major over a channel count padded to a multiple of 4
+// Packed weights: the B operand of every 32-wide K chunk of v_mfma_f32_16x16x32_bf16
+// in lane order, wb[((ct * nch + ch) * 64 + lane) * 8 + i] = B[k = 32 ch + 8 q + i][n = 16 ct + r],
+// K ordered tap-major over a channel count padded to a multiple of 8
 // (k = tap * cpad + c), zero outside the layer. TW: the input-gradient form.
 template <bool TW>
 __global__ __launch_bounds__(256) void k_conv3d_pack_weights(const float* __restrict__ w, short* __restrict__ wb,
                                                              int cin, int cout, int cpad, int nch, int ctiles) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)ctiles * nch * 256) return;
-  const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
-  const long cc = i >> 8;
+  if (i >= (long)ctiles * nch * 512) return;
+  const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+  const long cc = i >> 9;
   const int ch = (int)(cc % nch), ct = (int)(cc / nch);
-  const int k = ch * 16 + 4 * (lane >> 4) + e, n = ct * 16 + (lane & 15);
+  const int k = ch * 32 + 8 * (lane >> 4) + e, n = ct * 16 + (lane & 15);
   float v = 0.f;
   if (k < kTaps * cpad && n < cout) {
     const int tap = k / cpad, c = k - tap * cpad;
@@ -142,9 +144,10 @@ constexpr int kMaxCpadLds = 64;                            // larger layers use 
 constexpr int kMaxCt = 4;                                  // output-channel tiles per block
 
 // The input halo of a 16 x 4 x 1 output tile sits in LDS as bfloat16, channels
-// innermost ([dz][y][x][cpad]): the A operand of a lane (4 channels at one tap
-// of its voxel) is one 8-byte LDS read. The packed B operand is one 8-byte
-// global read per lane, the same for every block (cache-resident).
+// innermost ([dz][y][x][cpad]): the A operand of a lane (8 channels at one tap
+// of its voxel, v_mfma_f32_16x16x32_bf16: lane l holds row l & 15, K entries
+// 8 (l >> 4) .. + 7) is one 16-byte LDS read. The packed B operand is one
+// 16-byte global read per lane, the same for every block (cache-resident).
 __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x, const short* __restrict__ wb,
                                                     const float* __restrict__ bias, float* __restrict__ y, int nb,
                                                     int cin, int cout, int nz, int ny, int nx, int relu, int cpad,
@@ -152,8 +155,8 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   extern __shared__ __align__(16) unsigned char smem[];
   short* xs = reinterpret_cast<short*>(smem);
   const int halo = 3 * kHaloY * kHaloX * cpad;
-  int* qoff = reinterpret_cast<int*>(xs + halo);           // halo is a multiple of 4 elements
-  const int nq = kTaps * cpad / 4;
+  int* qoff = reinterpret_cast<int*>(xs + halo);           // halo is a multiple of 8 elements
+  const int nq = kTaps * cpad / 8;
   long t = blockIdx.x;
   const int xt = (int)(t % xtiles);
   t /= xtiles;
@@ -166,8 +169,8 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   const int x0 = xt * kTileX, y0 = yt * kTileY;
   const int tid = threadIdx.x;
   for (int j = tid; j < nq; j += 256) {
-    const int tap = j / (cpad / 4), cq = j - tap * (cpad / 4);
-    qoff[j] = (((tap / 9) * kHaloY + (tap / 3) % 3) * kHaloX + tap % 3) * cpad + 4 * cq;
+    const int tap = j / (cpad / 8), cq = j - tap * (cpad / 8);
+    qoff[j] = (((tap / 9) * kHaloY + (tap / 3) % 3) * kHaloX + tap % 3) * cpad + 8 * cq;
   }
   const long vol = (long)nz * ny * nx;
   const float* xb = x + (long)b * cin * vol;
@@ -190,15 +193,16 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   f32x4 acc[kMaxCt];
 #pragma unroll
   for (int c = 0; c < kMaxCt; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16x4 zero = {0, 0, 0, 0};
+  const bf16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int ch = 0; ch < nch; ++ch) {
     const int j = ch * 4 + q;
-    const bf16x4 a = j < nq ? *reinterpret_cast<const bf16x4*>(arow + qoff[j]) : zero;
+    const bf16x8 a = j < nq ? *reinterpret_cast<const bf16x8*>(arow + qoff[j]) : zero;
 #pragma unroll
     for (int c = 0; c < kMaxCt; ++c) {
       if (c < nct) {
-        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(wb + (((long)(ct0 + c) * nch + ch) * 64 + lane) * 4);
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[c], 0, 0, 0);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wb + (((long)(ct0 + c) * nch + ch) * 64 + lane) * 8);
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, bv),
+                                                         acc[c], 0, 0, 0);
       }
     }
   }
@@ -371,11 +375,11 @@ pat_status launched(const char* who) {
   return e == hipSuccess ? PAT_OK : pat::set_error(PAT_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
 }
 
-int conv_cpad(int cin) { return (cin + 3) / 4 * 4; }
-int conv_nch(int cin) { return (kTaps * conv_cpad(cin) + 15) / 16; }
+int conv_cpad(int cin) { return (cin + 7) / 8 * 8; }
+int conv_nch(int cin) { return (kTaps * conv_cpad(cin) + 31) / 32; }
 bool conv_uses_lds(int cin) { return conv_cpad(cin) <= kMaxCpadLds; }
 size_t conv_pack_bytes(int cin, int cout) {
-  return conv_uses_lds(cin) ? (size_t)((cout + 15) / 16) * conv_nch(cin) * 256 * sizeof(short) : 0;
+  return conv_uses_lds(cin) ? (size_t)((cout + 15) / 16) * conv_nch(cin) * 512 * sizeof(short) : 0;
 }
 
 template <bool TW>
@@ -390,14 +394,14 @@ pat_status launch_conv(const char* who, const float* x, const float* w, const fl
       return pat::set_error(PAT_ERR_NOMEM, "%s: workspace of %zu bytes needed", who, need);
     const int cpad = conv_cpad(cin), nch = conv_nch(cin), ctiles = (cout + 15) / 16;
     short* wb = (short*)workspace;
-    const long npack = (long)ctiles * nch * 256;
+    const long npack = (long)ctiles * nch * 512;
     hipLaunchKernelGGL(k_conv3d_pack_weights<TW>, dim3((unsigned)((npack + 255) / 256)), dim3(256), 0, st, w, wb, cin,
                        cout, cpad, nch, ctiles);
     const int xtiles = (nx + kTileX - 1) / kTileX, ytiles = (ny + kTileY - 1) / kTileY;
     const int cgroups = (ctiles + kMaxCt - 1) / kMaxCt;
     const long blocks = (long)nb * nz * cgroups * ytiles * xtiles;
     if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
-    const size_t lds = (size_t)3 * kHaloY * kHaloX * cpad * sizeof(short) + (size_t)(kTaps * cpad / 4) * sizeof(int);
+    const size_t lds = (size_t)3 * kHaloY * kHaloX * cpad * sizeof(short) + (size_t)(kTaps * cpad / 8) * sizeof(int);
     hipLaunchKernelGGL(k_conv3d_lds, dim3((unsigned)blocks), dim3(256), lds, st, x, wb, bias, y, nb, cin, cout, nz, ny,
                        nx, relu, cpad, nch, ctiles, xtiles, ytiles, cgroups);
     return launched(who);

@@ -47,9 +47,9 @@ def test_nn_validation_without_gpu():
     assert lib.pat_conv3d_backward_weight_workspace_bytes(2, 3, 20, 5, 6, 37) == 60 * 20 * 82 * 4
     assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 16, 16, 128, 128, 128) == 256 * 16 * 433 * 4
     assert lib.pat_conv3d_backward_weight_workspace_bytes(1, 0, 16, 8, 8, 8) == 0
-    # packed weights: ceil(co / 16) tiles x ceil(27 cpad / 16) chunks x 256 bfloat16, cpad = ci rounded up to 4
-    assert lib.pat_conv3d_workspace_bytes(3, 20) == max(2 * 7 * 512, 1 * 34 * 512)
-    assert lib.pat_conv3d_workspace_bytes(24, 24) == 2 * 41 * 512
+    # packed weights: ceil(co / 16) tiles x ceil(27 cpad / 32) chunks x 512 bfloat16, cpad = ci rounded up to 8
+    assert lib.pat_conv3d_workspace_bytes(3, 20) == max(2 * 7 * 1024, 1 * 21 * 1024)
+    assert lib.pat_conv3d_workspace_bytes(24, 24) == 2 * 21 * 1024
     assert lib.pat_conv3d_workspace_bytes(70, 70) == 256          # both directions use the unpacked kernel
     assert lib.pat_conv3d_workspace_bytes(0, 4) == 0
     assert lib.pat_conv3d_forward(None, None, None, None, 1, 0, 4, 8, 8, 8, 0, None, 0, None) == 1

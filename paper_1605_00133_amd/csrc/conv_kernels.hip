@@ -1,22 +1,25 @@
 // 3x3x3 convolution layers for a learned update step (outside the paper's
 // method: a network mapping the iterate and the gradient A^T C^T (C A p - f)
-// of eq. BP to the next iterate). BF16 operands on the matrix cores
-// (v_mfma_f32_16x16x16_bf16), FP32 accumulation, FP32 tensors in HBM.
+// of eq. BP to the next iterate). BF16 operands on the matrix cores, FP32
+// accumulation, FP32 tensors in HBM.
 //
 // Layout: activations [B][C][nz][ny][nx] (x fastest), weights [Co][Ci][3][3][3],
-// zero padding of one voxel ("same" size). Every entry point is a GEMM over
-// K = 27 Ci (k = ci * 27 + tap, tap = 9 (dz+1) + 3 (dy+1) + (dx+1)):
-//   forward       y[b][co][v]  = sum_k w[co][k] x[b][ci][v + d(tap)] (+ bias, ReLU)
+// zero padding of one voxel ("same" size). Every entry point is a GEMM over the
+// taps and input channels:
+//   forward       y[b][co][v]  = sum_{ci,tap} w[co][ci][tap] x[b][ci][v + d(tap)] (+ bias, ReLU)
 //   input grad    dx[b][ci][v] = sum_{co,tap} w[co][ci][tap] dy[b][co][v - d(tap)]
 //                 (the forward with w transposed over channels and the taps mirrored)
-//   weight grad   dw[co][k]    = sum_{b,v} dy[b][co][v] x[b][ci][v + d(tap)], db[co] = sum dy
+//   weight grad   dw[co][ci][tap] = sum_{b,v} dy[b][co][v] x[b][ci][v + d(tap)], db[co] = sum dy
+// with tap = 9 (dz+1) + 3 (dy+1) + (dx+1).
 //
-// MFMA 16x16x16 (64 lanes, lane l, r = l & 15, q = l >> 4): A operand rows
-// r, columns 4q..4q+3; B operand rows 4q..4q+3, column r; result rows 4q..4q+3
-// (one per accumulator register), column r. Each operand value is rounded to
-// BF16 (nearest even) when it is loaded; sums stay FP32. The weight gradient
-// writes one 16x16 partial per (chunk of rows, tile) and sums the chunks in a
-// fixed order in FP64: results do not depend on scheduling.
+// Matrix-core layouts (64 lanes, lane l, r = l & 15, q = l >> 4), result rows
+// 4q..4q+3 (one per accumulator register), column r in both:
+//   v_mfma_f32_16x16x16_bf16: A row r, K entries 4q..4q+3; B K entries 4q..4q+3, column r
+//   v_mfma_f32_16x16x32_bf16: A row r, K entries 8q..8q+7; B K entries 8q..8q+7, column r
+// Each operand value is rounded to BF16 (nearest even) when it is loaded or
+// staged; sums stay FP32. The weight gradient writes one 16x16 partial per
+// (chunk of rows, tile) and sums the chunks in a fixed order in FP64: results
+// do not depend on scheduling.
 
 #include <hip/hip_runtime.h>
 

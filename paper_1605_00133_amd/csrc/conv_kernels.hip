@@ -318,6 +318,121 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_conv3d_wgrad_partial(
   }
 }
 
+constexpr int kWgTiles = 8;   // (co tile, column tile) accumulators per wave of the LDS weight gradient
+constexpr int kMaxChLds = 64;  // channel limit of the LDS weight gradient
+
+// Weight-gradient partials with the operands in LDS. Block (chunk, tile group) sums the
+// row groups chunk, chunk + nchunk, ... (4 rows of one (b, z) plane each), 16 x
+// positions at a time: it stages that 4 x 16 tile of dy ([co][row][x], bfloat16) and
+// the tile's input halo ([ci][dz][y][x], bfloat16) in LDS, then each wave adds its up
+// to 8 tiles of the [co][ci * 27 + tap | bias] GEMM over the 64 voxels, one row (one
+// K chunk) at a time. The row loop stays rolled so that only one row's operands are
+// live (unrolled, the kernel needs 380 registers: one wave per SIMD). Partials as in
+// k_conv3d_wgrad_partial.
+__global__ __launch_bounds__(256) void k_conv3d_wgrad_lds(const float* __restrict__ x, const float* __restrict__ gy,
+                                                          float* __restrict__ part, int nb, int cin, int cout, int nz,
+                                                          int ny, int nx, int nchunk, int mtiles, int ntiles,
+                                                          int tgroups, int ytiles, int xtiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int cpo = mtiles * 16;
+  short* ds = reinterpret_cast<short*>(smem);                 // [cpo][kTileY][kTileX]
+  short* xh = ds + cpo * kTileY * kTileX;                     // [cin][3][kHaloY][kHaloX]
+  const int tg = (int)(blockIdx.x % tgroups), chunk = (int)(blockIdx.x / tgroups);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, q = lane >> 4;
+  const int ncol = cin * kTaps + 1, T = mtiles * ntiles;
+  const int tbase = (tg * 4 + wv) * kWgTiles;
+  int aoff[kWgTiles], boff[kWgTiles], kind[kWgTiles];
+#pragma unroll
+  for (int s = 0; s < kWgTiles; ++s) {
+    const int t = tbase + s;
+    const int mt = t / ntiles, nt = t - mt * ntiles, n = nt * 16 + r;
+    aoff[s] = (mt * 16 + r) * kTileY * kTileX;
+    kind[s] = 2;   // zero column
+    boff[s] = 0;
+    if (t < T && n < ncol - 1) {
+      const int ci = n / kTaps, tap = n - ci * kTaps;
+      boff[s] = ((ci * 3 + tap / 9) * kHaloY + (tap / 3) % 3) * kHaloX + tap % 3;
+      kind[s] = 0;
+    } else if (t < T && n == ncol - 1) {
+      kind[s] = 1;   // bias column: ones
+    }
+  }
+  f32x4 acc[kWgTiles];
+#pragma unroll
+  for (int s = 0; s < kWgTiles; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const long vol = (long)nz * ny * nx;
+  const long groups = (long)nb * nz * ytiles;
+  const int nds = cpo * kTileY * kTileX, nxh = cin * 3 * kHaloY * kHaloX;
+  const short one = 0x3f80;   // 1.0 in bfloat16
+  for (long g = chunk; g < groups; g += nchunk) {
+    const int yt = (int)(g % ytiles);
+    const int zz = (int)((g / ytiles) % nz);
+    const int b = (int)(g / ((long)ytiles * nz));
+    const int y0 = yt * kTileY;
+    for (int xt = 0; xt < xtiles; ++xt) {
+      const int x0 = xt * kTileX;
+      __syncthreads();   // the previous tile's reads are done
+      for (int i = tid; i < nds; i += 256) {
+        const int xx = i % kTileX, rest = i / kTileX;
+        const int ry = rest % kTileY, co = rest / kTileY;
+        float v = 0.f;
+        if (co < cout && y0 + ry < ny && x0 + xx < nx)
+          v = gy[((long)b * cout + co) * vol + ((long)zz * ny + y0 + ry) * nx + x0 + xx];
+        ds[i] = bf16_rne(v);
+      }
+      for (int i = tid; i < nxh; i += 256) {
+        const int hx = i % kHaloX;
+        int rest = i / kHaloX;
+        const int hy = rest % kHaloY;
+        rest /= kHaloY;
+        const int hz = rest % 3, c = rest / 3;
+        const int gz = zz + hz - 1, gyy = y0 + hy - 1, gx = x0 + hx - 1;
+        float v = 0.f;
+        if (gz >= 0 && gz < nz && gyy >= 0 && gyy < ny && gx >= 0 && gx < nx)
+          v = x[((long)b * cin + c) * vol + ((long)gz * ny + gyy) * nx + gx];
+        xh[i] = bf16_rne(v);
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int ry = 0; ry < kTileY; ++ry) {
+#pragma unroll
+        for (int s = 0; s < kWgTiles; ++s) {
+          if (tbase + s < T) {   // wave-uniform
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(ds + aoff[s] + ry * kTileX + 4 * q);
+            bf16x4 bv = {0, 0, 0, 0};
+            if (kind[s] == 0) {
+              const short* src = xh + boff[s] + ry * kHaloX + 4 * q;
+              bv[0] = src[0];
+              bv[1] = src[1];
+              bv[2] = src[2];
+              bv[3] = src[3];
+            } else if (kind[s] == 1) {
+              bv[0] = one;
+              bv[1] = one;
+              bv[2] = one;
+              bv[3] = one;
+            }
+            acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[s], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  float* p = part + (long)chunk * cout * ncol;
+#pragma unroll
+  for (int s = 0; s < kWgTiles; ++s) {
+    const int t = tbase + s;
+    if (t >= T) continue;
+    const int mt = t / ntiles, nt = t - mt * ntiles, n = nt * 16 + r;
+    if (n >= ncol) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = mt * 16 + 4 * q + i;
+      if (co < cout) p[(long)co * ncol + n] = acc[s][i];
+    }
+  }
+}
+
 // dw[co][k] = sum over the chunks (FP64, fixed order: 16 interleaved partial sums per
 // column, then those 16 in order); the last column goes to db. Block: 16 columns x 16.
 __global__ __launch_bounds__(256) void k_conv3d_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw,
@@ -468,13 +583,22 @@ pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw
   if (!workspace || workspace_bytes < need)
     return pat::set_error(PAT_ERR_NOMEM, "pat_conv3d_backward_weight: workspace of %zu bytes needed", need);
   const long rows = (long)batch * nz * ny;
-  const int nc = nchunks(rows < 1 ? 1 : rows);
+  int nc = nchunks(rows < 1 ? 1 : rows);
   const int mtiles = (c_out + 15) / 16, ntiles = (c_in * kTaps + 1 + 15) / 16;
   // sharing dy pays when there are many column tiles; with few, one tile per wave keeps more waves
   const int ncw = ntiles >= 16 ? kWgCols : 1;
   const int ngroups = (ntiles + ncw - 1) / ncw;
   float* part = (float*)workspace;
-  if (rows > 0) {
+  if (rows > 0 && c_in <= kMaxChLds && c_out <= kMaxChLds) {
+    const int ytiles = (ny + kTileY - 1) / kTileY, xtiles = (nx + kTileX - 1) / kTileX;
+    const long groups = (long)batch * nz * ytiles;
+    nc = (int)(groups < kChunks ? groups : kChunks);   // <= nchunks(rows): fits the workspace
+    const int tgroups = (mtiles * ntiles + 4 * kWgTiles - 1) / (4 * kWgTiles);
+    const size_t lds = ((size_t)mtiles * 16 * kTileY * kTileX + (size_t)c_in * 3 * kHaloY * kHaloX) * sizeof(short);
+    hipLaunchKernelGGL(k_conv3d_wgrad_lds, dim3((unsigned)((long)nc * tgroups)), dim3(256), lds, (hipStream_t)stream, x,
+                       dy, part, batch, c_in, c_out, nz, ny, nx, nc, mtiles, ntiles, tgroups, ytiles, xtiles);
+    PAT_NN_CHECK(launched("pat_conv3d_backward_weight"));
+  } else if (rows > 0) {
     const long waves = (long)nc * mtiles * ngroups;
     hipLaunchKernelGGL(k_conv3d_wgrad_partial, dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock)),
                        dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, x, dy, part, batch, c_in, c_out, nz, ny, nx,

@@ -9,8 +9,9 @@ or chunked FP32 sums of a few hundred terms added in FP64 for the weights).
 Sizes are ragged against the 16 x 16 tiles and the 16 x 4 output tiles of a
 block (x extent 37, y extent 7, 20 output channels, K = 27 * 3 = 81), cover
 both forward kernels (packed operands with the input halo in LDS for up to 64
-padded input channels, the unpacked kernel above) and the shapes of the
-learned update network.
+padded input channels, the unpacked kernel above), both weight-gradient kernels
+(operands in LDS for up to 64 channels each way, gathered from global memory
+above) and the shapes of the learned update network.
 """
 
 import numpy as np

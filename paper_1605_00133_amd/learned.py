@@ -186,8 +186,12 @@ def experiment(n=32, n_train=24, n_test=6, n_steps=5, epochs=150, channels=16, w
     targets = [torch.empty(plans[0].vol_shape, dtype=torch.float32, device=dev) for _ in range(total)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reconstruct_all(plans, fs, targets, [10 * lam for lam in lams], [L] * total, workers=workers, n_outer=5,
-                    n_inner=50, n_prox=50)
+    for c0 in range(0, total, workers):   # in chunks, so that progress is reported on large grids
+        c1 = min(c0 + workers, total)
+        reconstruct_all(plans[c0:c1], fs[c0:c1], targets[c0:c1], [10 * lam for lam in lams[c0:c1]], [L] * (c1 - c0),
+                        workers=workers, n_outer=5, n_inner=50, n_prox=50)
+        if log and total > workers:
+            log(f"targets {c1}/{total}")
     torch.cuda.synchronize()
     if log:
         log(f"{total} TV+Br targets in {time.perf_counter() - t0:.1f} s, L = {L:.4e}")

@@ -9,7 +9,7 @@
  *   p = A^T C^T f                  back-projection / gradient, eq. (BP), Sec. 4.4
  *   q = prox_{TV + (q>=0), alpha}  positivity-constrained TV denoising, eq. (Prox), App. A/B
  *   p = argmin 1/2||CAp - f||^2 + lambda TV(p), p >= 0   eq. (VarReg)/(TV+), by FISTA (App. B)
- *       optionally enhanced by Bregman iterations, eq. (BregIterA/B), Sec. 4.5
+ *       optionally enhanced by Bregman iterations, eq. (BregIterA/B), Sec. 4.6
  *
  * where A is 3D linear acoustic propagation of the initial pressure
  * (eq. PATfwd) by a k-space pseudospectral scheme with a perfectly matched

@@ -12,7 +12,7 @@ Modules
   operator  forward operator A and its exact adjoint (eq. PATfwd, Sec. 4.3)
   sampling  SplitMix64 masks, scrambled Hadamard patterns, C and C^T (Sec. 3.1, 4.3)
   tv        discrete isotropic TV and its PDHG proximal operator (App. A, App. B)
-  solvers   FISTA with restart/backtracking, Bregman, power iteration (App. B, Sec. 4.5)
+  solvers   FISTA with restart/backtracking, Bregman, power iteration (App. B, Sec. 4.6)
   metrics   thresholded PSNR (eq. PSNR)
   dense     explicit-matrix brute force of A for tiny grids (pins the FFT operator)
 

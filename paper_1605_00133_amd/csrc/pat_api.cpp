@@ -1,6 +1,6 @@
 // C ABI of the photoacoustic-tomography hot path: plan set-up (FP64 tables,
 // workspace carve-up), argument validation, the operator entry points and the
-// host driver of FISTA / Bregman (App. B, Sec. 4.5). All device work is
+// host driver of FISTA / Bregman (App. B, Sec. 4.6). All device work is
 // enqueued on the plan's stream; only calls that return host scalars sync.
 #include <hip/hip_runtime.h>
 

@@ -49,15 +49,34 @@ def adjoint_all(plans, fs, ps):
     _join(cur, streams)
 
 
-def reconstruct_all(plans, fs, ps, lams, Ls, workers=None, **kwargs):
+def _warm(plans, fs, ps):
+    """One short reconstruction per distinct plan shape on the calling thread, before
+    any worker starts, so that the first launch of every kernel a reconstruction
+    uses (and the runtime's loading of its code) happens on one thread and not
+    concurrently in the workers. Writes only ps[k] of the first plan of each shape,
+    which the workers overwrite."""
+    seen = set()
+    for plan, f, p in zip(plans, fs, ps):
+        g = plan.grid
+        key = (g.nx, g.ny, g.nz, g.nt, plan.kind)
+        if key in seen:
+            continue
+        seen.add(key)
+        P.pat_reconstruct(plan, f, p, 0.0, 1.0, n_outer=1, n_inner=1, n_prox=1, restart=False)
+
+
+def reconstruct_all(plans, fs, ps, lams, Ls, workers=None, warm=True, **kwargs):
     """pat_reconstruct(plans[k], fs[k], ps[k], lams[k], Ls[k], **kwargs) for every k.
     `workers` host threads (default: one per problem), each with a stream of its
     own, take the problems in list order (put the largest first to balance mixed
-    sizes). Returns the list of logs. The first error raised by any problem is
-    raised again here, after all workers have ended; problems not yet started
-    by then are skipped."""
+    sizes). With more than one worker and `warm`, one short reconstruction per
+    distinct plan shape runs first on the calling thread (_warm). Returns the
+    list of logs. The first error raised by any problem is raised again here,
+    after all workers have ended; problems not yet started by then are skipped."""
     n = len(plans)
     workers = n if workers is None else max(1, min(int(workers), n))
+    if workers > 1 and warm:
+        _warm(plans, fs, ps)
     cur, streams = _streams(plans[:workers])
     outs, errs = [None] * n, [None] * n
     lock = threading.Lock()
@@ -134,14 +153,13 @@ def dynamic_scan(sizes=(64,), n_frames=24, iters=30, workers=4, rate=8, n_prox=5
     torch.cuda.synchronize()
     log(f"{n_frames} frames, sizes {dict((n, frame_n.count(n)) for n in sorted(set(frame_n)))}, L {L_of}")
     kw = dict(n_outer=1, n_inner=iters, n_prox=n_prox, bc="dirichlet", restart=True)
-    warm = [torch.empty(plans[0].vol_shape, dtype=torch.float32, device=dev)]
-    reconstruct_all(plans[:1], fs[:1], warm, lams[:1], Ls[:1], n_outer=1, n_inner=2, n_prox=n_prox)
+    _warm(plans, fs, [torch.empty(pl.vol_shape, dtype=torch.float32, device=dev) for pl in plans])
     res = {}
     for w in (1, workers):
         ps = [torch.empty(pl.vol_shape, dtype=torch.float32, device=dev) for pl in plans]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        reconstruct_all(plans, fs, ps, lams, Ls, workers=w, **kw)
+        reconstruct_all(plans, fs, ps, lams, Ls, workers=w, warm=False, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[w] = (n_frames / dt, ps)

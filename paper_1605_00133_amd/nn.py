@@ -8,6 +8,7 @@ torch autograd function.
 """
 
 import ctypes as C
+import threading
 
 import torch
 
@@ -26,17 +27,22 @@ SIGNATURES = {
 }
 
 _bound = False
+_bind_lock = threading.Lock()
 
 
 def lib():
+    """libpat.so with the layer signatures bound (once, under a lock, so that
+    concurrent first callers never see a half-bound library)."""
     global _bound
     L = P.lib()
     if not _bound:
-        for name, (res, args) in SIGNATURES.items():
-            fn = getattr(L, name)
-            fn.restype = res
-            fn.argtypes = args
-        _bound = True
+        with _bind_lock:
+            if not _bound:
+                for name, (res, args) in SIGNATURES.items():
+                    fn = getattr(L, name)
+                    fn.restype = res
+                    fn.argtypes = args
+                _bound = True
     return L
 
 

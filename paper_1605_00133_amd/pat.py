@@ -9,6 +9,7 @@ The module raises at import of the library if libpat.so has not been built.
 
 import ctypes as C
 import os
+import threading
 
 import numpy as np
 
@@ -84,6 +85,7 @@ SIGNATURES = {
 }
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def lib():
@@ -92,19 +94,23 @@ def lib():
     torch is imported first so that its bundled HIP runtime is the only one in
     the process: libpat.so then binds to it by soname instead of mapping a
     second runtime from /opt/rocm, which would fail to initialise next to
-    torch's.
+    torch's. Thread-safe: the first caller loads and binds under a lock, and
+    the handle is published only once every signature is set.
     """
     global _lib
-    if _lib is None:
-        import torch  # noqa: F401  (load order matters, see docstring)
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1605_00133_amd.build`")
-        L = C.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
-            fn = getattr(L, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = L
+    if _lib is not None:
+        return _lib
+    with _lib_lock:
+        if _lib is None:
+            import torch  # noqa: F401  (load order matters, see docstring)
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1605_00133_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
     return _lib
 
 

@@ -121,3 +121,52 @@ def test_tv_dual_floats():
     g = _grid()
     assert P.pat_tv_dual_floats(g, "neumann") == 3 * 32 ** 3
     assert P.pat_tv_dual_floats(g, "dirichlet") == 3 * 33 ** 3
+
+
+def test_plan_create_workspace_checks_without_gpu():
+    """Workspace errors are found before the library touches the GPU (no device needed)."""
+    g = _grid()
+    smp, keep = P.make_sampling("full", 32 * 32)
+    need = P.pat_plan_workspace_bytes(g, smp)
+    h = C.c_void_p()
+    lib = P.lib()
+    assert lib.pat_plan_create(C.byref(g), C.byref(smp), None, None, need, C.byref(h)) == 1
+    assert b"workspace is NULL" in lib.pat_last_error()
+    assert lib.pat_plan_create(C.byref(g), C.byref(smp), None, C.c_void_p(0x10000 + 8), need, C.byref(h)) == 1
+    assert b"aligned" in lib.pat_last_error()
+    assert lib.pat_plan_create(C.byref(g), C.byref(smp), None, C.c_void_p(0x10000), need - 1, C.byref(h)) == 3
+    assert b"workspace has" in lib.pat_last_error()
+    assert not h.value
+    assert lib.pat_plan_create(C.byref(g), C.byref(smp), None, None, 0, None) == 1
+
+
+def test_concurrent_first_load_binds_once():
+    """Threads that load the library at the same moment all get one fully bound handle."""
+    import threading
+    from paper_1605_00133_amd import nn
+    P.lib()
+    saved = P._lib
+    try:
+        for _ in range(5):
+            P._lib = None
+            nn._bound = False
+            start = threading.Barrier(8)
+            got = []
+
+            def load():
+                start.wait()
+                L = nn.lib()
+                got.append((L, L.pat_conv3d_forward.restype, L.pat_forward.argtypes))
+
+            ts = [threading.Thread(target=load) for _ in range(8)]
+            for t in ts:
+                t.start()
+            for t in ts:
+                t.join()
+            assert len(got) == 8
+            assert len({id(L) for L, _, _ in got}) == 1
+            assert all(r is C.c_int and a is not None for _, r, a in got)
+    finally:
+        P._lib = saved
+        nn._bound = False
+        nn.lib()

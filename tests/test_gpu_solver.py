@@ -5,6 +5,9 @@ Tolerances: prox and reconstructions at fixed iteration counts within 1e-4
 relative L2; scalars (TV, PSNR, L) within FP32 rounding of their inputs.
 """
 
+import math
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +21,14 @@ from gpu_cases import (empty, gaussian_data, gaussian_volume, gpu_plan, oracle_g
 pytestmark = pytest.mark.gpu
 
 TOL_RECON = 1e-4
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fixture(name):
+    path = os.path.join(GOLDEN, f"{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {path} not generated")
+    return np.load(path)
 
 
 def _oracle_dual_to_gpu(y, bc):
@@ -75,6 +86,35 @@ def test_psnr_matches_oracle():
     print(f"PSNR {got} vs {ref}")
     assert abs(got - ref) < 1e-9 * abs(ref)
     assert P.pat_psnr(plan, to_dev(a), to_dev(a)) == float("inf")
+
+
+def test_psnr_evaluation_region_worked_example():
+    """The GPU's evaluation region, pinned by hand (independently of the oracle's eval_region).
+
+    16^3 grid, P = 2: z in [1, nz - 2P) = [1, 12), y and x in [2, 14), N = 11 * 12 * 12 = 1584.
+    Large values on the sensor layer, the first z-PML layer, deep in the z-PML and one cell
+    into each lateral PML face would set the maximum if they were inside. Inside, p differs from
+    p0 by 0.5 at the first corner and 0.25 at the last: PSNR = -10 log10(0.3125 / 1584).
+    """
+    from paper_1605_00133_amd import pat as P
+    n = 16
+    plan = gpu_plan(n, 2, oracle_sampling("full", n), pml=2)
+    p0 = np.zeros((n, n, n))
+    p0[5, 7, 7] = 1.0
+    p0[0, 8, 8] = 9.0
+    p0[13, 8, 8] = 9.0
+    p = p0.copy()
+    p[0, 8, 8] = p[13, 8, 8] = 0.0
+    p[0, 7, 7] = 50.0
+    p[12, 7, 7] = 40.0
+    p[15, 7, 7] = 30.0
+    p[5, 1, 7] = p[5, 14, 7] = p[5, 7, 1] = p[5, 7, 14] = 20.0
+    p[1, 2, 2] = 0.5
+    p[11, 13, 13] = 0.25
+    got = P.pat_psnr(plan, to_dev(p), to_dev(p0))
+    ref = -10 * math.log10(0.3125 / 1584)
+    print(f"PSNR region example: {got!r} vs {ref!r}")
+    assert abs(got - ref) < 1e-9 * ref
 
 
 def test_power_iteration_matches_oracle():
@@ -137,3 +177,34 @@ def test_bregman_matches_oracle_and_residual_decreases():
     assert err < TOL_RECON
     assert np.allclose(out["bregman_residual"], res, rtol=1e-4)
     assert np.all(np.diff(out["bregman_residual"]) < 0)
+
+
+def test_fista_restart_branch_matches_oracle():
+    """The restart + backtracking branch of App. B on the GPU against the oracle.
+
+    The oracle run is stored by tests/golden/make_solver_fixtures.py (restart32_points): the
+    small workload with L underestimated 3x, so the energy rises and the branch runs in most
+    iterations (plain gradient step from the previous iterate, halvings, t reset). The data
+    are recomputed here by the oracle with the stored sigma. Flags must be identical, with
+    at least one halving; energies and the reconstruction within 1e-4.
+    """
+    from paper_1605_00133_amd import pat as P
+    fx = _fixture("restart32_points")
+    n, nt = 32, 190
+    smp = oracle_sampling("points", n)
+    op = MeasuredOperator(oracle.WaveOperator(oracle_grid(n, nt)), smp)
+    p0 = phantom(n)
+    clean = op.forward(p0)
+    f = clean + float(fx["sigma"]) * gaussian_data(clean.shape, 3)
+    plan = gpu_plan(n, nt, smp)
+    p = empty(plan.vol_shape)
+    out = P.pat_reconstruct(plan, to_dev(f), p, float(fx["lam"]), float(fx["L"]), 1, 10, 50, "dirichlet",
+                            restart=True)
+    err = rel_l2(to_host(p), fx["x"])
+    print(f"FISTA forced restarts: rel L2 {err:.2e}; flags GPU {list(out['flags'])} oracle {list(fx['flags'])}")
+    print("energies GPU", out["energy"], "oracle", fx["energy"])
+    assert list(out["flags"]) == list(fx["flags"])
+    assert max(fx["flags"]) >= 2
+    assert np.allclose(out["energy"], fx["energy"], rtol=1e-4)
+    assert np.allclose(out["residual"], fx["residual"], rtol=1e-4)
+    assert err < TOL_RECON

@@ -48,6 +48,25 @@ pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias,
                               int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pat_conv3d_forward
+ * with no workspace argument. The bfloat16-packed weights go to a device array
+ * of PAT_CONV_STATIC_SCRATCH_BYTES inside the library, one per GPU, allocated
+ * with the library's code and held until the process ends; nothing is
+ * allocated by the call. Its device address is looked up once per GPU (first
+ * call on that GPU, under a lock). Layers whose packed weights need more bytes
+ * than the array holds (at most 64 (padded) input channels take the packed
+ * path; e.g. 64 -> 256 channels needs 884 736 bytes) are rejected with
+ * PAT_ERR_INVALID before anything is enqueued; wider inputs take the unpacked
+ * path and use no scratch. Every call on one GPU shares the array and
+ * overwrites it before use: calls that overlap in time on one GPU (different
+ * streams or threads) race and may read each other's weights, so order them
+ * (one stream, or events). Results equal pat_conv3d_forward's bit for bit. */
+#define PAT_CONV_STATIC_SCRATCH_BYTES (1u << 20)
+pat_status pat_conv3d_forward_static(const float* x, const float* w, const float* bias, float* y, int32_t batch,
+                                     int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
+                                     void* stream);
+
 /* dx = gradient of sum(dy * conv(x, w)) with respect to x: the adjoint of the
  * convolution (weights transposed over channels, taps mirrored).
  * dy [batch][c_out][...], dx [batch][c_in][...] (overwritten); no overlap.

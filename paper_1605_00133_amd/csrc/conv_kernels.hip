@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/pat_nn.h"
 #include "pat_internal.hpp"
@@ -511,14 +512,14 @@ pat_status launch_conv(const char* who, const float* x, const float* w, const fl
     if (!workspace || workspace_bytes < need)
       return pat::set_error(PAT_ERR_NOMEM, "%s: workspace of %zu bytes needed", who, need);
     const int cpad = conv_cpad(cin), nch = conv_nch(cin), ctiles = (cout + 15) / 16;
-    short* wb = (short*)workspace;
-    const long npack = (long)ctiles * nch * 512;
-    hipLaunchKernelGGL(k_conv3d_pack_weights<TW>, dim3((unsigned)((npack + 255) / 256)), dim3(256), 0, st, w, wb, cin,
-                       cout, cpad, nch, ctiles);
     const int xtiles = (nx + kTileX - 1) / kTileX, ytiles = (ny + kTileY - 1) / kTileY;
     const int cgroups = (ctiles + kMaxCt - 1) / kMaxCt;
     const long blocks = (long)nb * nz * cgroups * ytiles * xtiles;
     if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
+    short* wb = (short*)workspace;
+    const long npack = (long)ctiles * nch * 512;
+    hipLaunchKernelGGL(k_conv3d_pack_weights<TW>, dim3((unsigned)((npack + 255) / 256)), dim3(256), 0, st, w, wb, cin,
+                       cout, cpad, nch, ctiles);
     const size_t lds = (size_t)3 * kHaloY * kHaloX * cpad * sizeof(short) + (size_t)(kTaps * cpad / 8) * sizeof(int);
     hipLaunchKernelGGL(k_conv3d_lds, dim3((unsigned)blocks), dim3(256), lds, st, x, wb, bias, y, nb, cin, cout, nz, ny,
                        nx, relu, cpad, nch, ctiles, xtiles, ytiles, cgroups);
@@ -531,6 +532,48 @@ pat_status launch_conv(const char* who, const float* x, const float* w, const fl
   hipLaunchKernelGGL(k_conv3d<TW>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, st, x, w, bias, y, nb, cin,
                      cout, nz, ny, nx, relu, xtiles, ctiles);
   return launched(who);
+}
+
+// Packed weights of pat_conv3d_forward_static: a file-scope device array, one
+// copy per GPU, held until the process ends. Host code never passes its name to
+// a kernel (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[PAT_CONV_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the device of `st` (the current device for the
+// null stream); found with that device current, then kept.
+pat_status static_scratch(hipStream_t st, void** out) {
+  int dev = -1;
+  if (st) {
+    hipDevice_t d = -1;
+    const hipError_t e = hipStreamGetDevice(st, &d);
+    if (e != hipSuccess) return pat::set_error(PAT_ERR_HIP, "hipStreamGetDevice: %s", hipGetErrorString(e));
+    dev = d;
+  } else {
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return pat::set_error(PAT_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return pat::set_error(PAT_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d", dev,
+                          kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return pat::set_error(PAT_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PAT_OK;
 }
 
 }  // namespace
@@ -552,6 +595,23 @@ pat_status pat_conv3d_forward(const float* x, const float* w, const float* bias,
   if (batch > 0 && (!x || !w || !y)) return pat::set_error(PAT_ERR_INVALID, "pat_conv3d_forward: null pointer");
   return launch_conv<false>("pat_conv3d_forward", x, w, bias, y, batch, c_in, c_out, nz, ny, nx, relu ? 1 : 0,
                             workspace, workspace_bytes, stream);
+}
+
+pat_status pat_conv3d_forward_static(const float* x, const float* w, const float* bias, float* y, int32_t batch,
+                                     int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx, int32_t relu,
+                                     void* stream) {
+  static const char* who = "pat_conv3d_forward_static";
+  PAT_NN_CHECK(conv_args(who, batch, c_in, c_out, nz, ny, nx));
+  if (batch > 0 && (!x || !w || !y)) return pat::set_error(PAT_ERR_INVALID, "%s: null pointer", who);
+  const size_t need = conv_pack_bytes(c_in, c_out);
+  if (need > PAT_CONV_STATIC_SCRATCH_BYTES)
+    return pat::set_error(PAT_ERR_INVALID, "%s: the layer's packed weights need %zu bytes, the static scratch holds %zu",
+                          who, need, (size_t)PAT_CONV_STATIC_SCRATCH_BYTES);
+  if (batch == 0) return PAT_OK;
+  void* ws = nullptr;
+  PAT_NN_CHECK(static_scratch((hipStream_t)stream, &ws));
+  return launch_conv<false>(who, x, w, bias, y, batch, c_in, c_out, nz, ny, nx, relu ? 1 : 0, ws,
+                            PAT_CONV_STATIC_SCRATCH_BYTES, stream);
 }
 
 pat_status pat_conv3d_backward_input(const float* dy, const float* w, float* dx, int32_t batch, int32_t c_in,

@@ -19,6 +19,7 @@ _I = C.c_int32
 SIGNATURES = {
     "pat_conv3d_workspace_bytes": (C.c_size_t, [_I, _I]),
     "pat_conv3d_forward": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
+    "pat_conv3d_forward_static": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _I, _P]),
     "pat_conv3d_backward_input": (C.c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
     "pat_conv3d_backward_weight_workspace_bytes": (C.c_size_t, [_I, _I, _I, _I, _I, _I]),
     "pat_conv3d_backward_weight": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
@@ -85,6 +86,19 @@ def conv3d_forward(x, w, bias=None, relu=False):
     ws, nbytes = _workspace(ci, co, x.device)
     P._check(lib().pat_conv3d_forward(_ptr(x, "x"), _ptr(w, "w", device=x.device), bp, _ptr(y, "y"), nb, ci, co,
                                       nz, ny, nx, 1 if relu else 0, C.c_void_p(ws.data_ptr()), nbytes, _stream(x)))
+    return y
+
+
+def conv3d_forward_static(x, w, bias=None, relu=False, out=None):
+    """As conv3d_forward through pat_conv3d_forward_static: no workspace, the packed
+    weights go to the library's own per-GPU array. Writes `out` when given (so a
+    caller under graph capture allocates nothing here) and returns it."""
+    nb, ci, co, nz, ny, nx = _sizes(x, w)
+    y = torch.empty((nb, co, nz, ny, nx), dtype=torch.float32, device=x.device) if out is None else out
+    bp = None if bias is None else _ptr(bias, "bias", (co,), x.device)
+    P._check(lib().pat_conv3d_forward_static(_ptr(x, "x"), _ptr(w, "w", device=x.device), bp,
+                                             _ptr(y, "y", (nb, co, nz, ny, nx), x.device), nb, ci, co, nz, ny, nx,
+                                             1 if relu else 0, _stream(x)))
     return y
 
 

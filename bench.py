@@ -1,18 +1,29 @@
-"""Benchmark: fwd+adj operator pairs/s at 128^3 inside the TV(+Bregman) FISTA loop.
+"""Benchmark: fwd+adj operator pairs/s at 128^3 inside TV-Bregman FISTA, and the
+time to target PSNR of plain TV-Bregman.
 
-A step is one FISTA iteration of the reconstruction at the paper's grid
-(128^3 incl. 8-cell PML, 128x128 sensor plane, Nt = 740, CFL 0.3): A^T C^T of
-the extrapolated residual, the gradient step, the positivity-constrained TV
-prox (50 PDHG iterations, Dirichlet TV), A and C of the new iterate, the FP64
-energy/residual/TV/PSNR reductions and the FISTA extrapolation in image and
-data space, with restart + backtracking enabled; the call ends with the
-Bregman update. value = forward/adjoint pairs executed per second (one pair
-per iteration plus the pairs of any restart; the loop starts from p = 0, whose
-residual -f needs no operator application).
+Workload (paper_1605_00133_amd.workload): the paper's grid (128^3 incl. 8-cell
+PML, 128x128 detection plane, Nt = 740, CFL 0.3), 24 random vessels (radius 1-4
+voxels), random 12.5 % single points (2048 of 16384 pixels, default) or 2048
+scrambled Hadamard patterns (--sampling hadamard), 1 % Gaussian noise;
+lambda_Br = 10 lambda_TV+, lambda_TV+ fixed beforehand by the discrepancy
+principle (eq. DiscPr) and frozen in synthetic.CONFIGS.
 
-Inputs are synthetic and already resident in HBM: 24 random vessels (radius
-1-4 voxels), random 12.5 % single points (2048 of 16384 pixels, default) or
-2048 scrambled Hadamard patterns (--sampling hadamard), 1 % Gaussian noise.
+A step is one FISTA iteration of the first TV+Br outer step: A^T C^T of the
+extrapolated residual, the gradient step, the positivity-constrained TV prox
+(50 PDHG iterations, Dirichlet TV), A and C of the new iterate, the FP64
+energy/residual/TV/PSNR reductions and the extrapolation in image and data
+space, with restart + backtracking on. value = forward/adjoint pairs executed
+per second (one pair per iteration plus the pairs of any restart; the loop
+starts from p = 0, whose residual -f needs no operator application).
+
+Besides the value (all outside the timed region): operator-only pairs/s; the
+per-kernel HIP-event timing of one pair (roofline of the dominant kernel); the
+error of this run's A and A^T against stored FP64 oracle samples; the other
+sampling mode's rates; 2 and 4 independent problems at once (4 x 0.5 GB is
+above the 256 MB last-level cache); the time-to-target curve of plain TV+Br
+(5 x 50, PSNR and wall time per iteration) and, when trained weights are
+present, the learned reconstruction against it; the FP64 oracle timed on the
+host (all cores and one core).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -32,6 +43,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adj operator pairs/s at 128^3; time-to-target-PSNR vs plain TV-Bregman"
 HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
@@ -70,23 +82,120 @@ def measured_traffic(kernel_name, src_hash):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n, nt, p0, smp_kind, mc, idx, perm, steps):
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def fp64_error(P, torch, prob):
+    """Relative L2 error of this run's A and A^T against the FP64 oracle samples stored
+    by tests/golden/make_operator_fixtures.py (None where the fixture is absent)."""
+    from synthetic import gaussian_data
+    kind, plan, dev = prob["sampling"], prob["plan"], prob["f"].device
+    out = {}
+    path = os.path.join(GOLDEN, f"op128_forward_{kind}.npz")
+    if prob["n"] == 128 and prob["nt"] == 740 and os.path.exists(path):
+        fx = np.load(path)
+        f = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+        P.pat_forward(plan, prob["p0"], f)
+        fh = f.cpu().numpy().astype(np.float64)
+        out["forward_sampled_columns"] = rel_l2(fh[:, fx["cols"]], fx["values"])
+        out["forward_norm"] = abs(np.linalg.norm(fh) - float(fx["norm"])) / float(fx["norm"])
+    path = os.path.join(GOLDEN, f"op128_adjoint_{kind}.npz")
+    if prob["n"] == 128 and prob["nt"] == 740 and os.path.exists(path):
+        fx = np.load(path)
+        y = torch.from_numpy(gaussian_data(plan.data_shape, int(fx["data_seed"])).astype(np.float32)).to(dev)
+        p = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+        P.pat_adjoint(plan, y, p)
+        ph = p.cpu().numpy().astype(np.float64)
+        out["adjoint_sampled_slices"] = rel_l2(ph[fx["zs"]], fx["values"])
+        out["adjoint_norm"] = abs(np.linalg.norm(ph) - float(fx["norm"])) / float(fx["norm"])
+    return out or None
+
+
+def fista_rate(P, torch, prob, steps, warmup, n_prox):
+    """`steps` FISTA iterations of the first TV+Br outer step, timed; returns (pairs, seconds, log)."""
+    plan, f = prob["plan"], prob["f"]
+    p = torch.empty(plan.vol_shape, dtype=torch.float32, device=f.device)
+
+    def run(iters):
+        return P.pat_reconstruct(plan, f, p, prob["lam_br"], prob["L"], n_outer=1, n_inner=iters, n_prox=n_prox,
+                                 bc="dirichlet", restart=True, p_ref=prob["p0"])
+
+    if warmup > 0:
+        run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = run(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    flags = out["flags"]
+    n_fwd = steps + int(flags.sum())
+    n_adj = steps + int((flags > 0).sum())
+    return 0.5 * (n_fwd + n_adj), elapsed, out
+
+
+def operator_rate(P, torch, prob, pairs=3):
+    plan, dev = prob["plan"], prob["f"].device
+    g = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+    ftmp = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+    P.pat_forward(plan, prob["p0"], ftmp)
+    P.pat_adjoint(plan, ftmp, g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(pairs):
+        P.pat_forward(plan, prob["p0"], ftmp)
+        P.pat_adjoint(plan, ftmp, g)
+    torch.cuda.synchronize()
+    return pairs / (time.perf_counter() - t)
+
+
+def concurrent_rate(P, torch, prob, K, reps=2):
+    """Aggregate operator pairs/s of K independent problems (own plan, phantom, stream)."""
+    from synthetic import vessel_phantom
+    dev = prob["f"].device
+    n, grid = prob["n"], prob["plan"].grid
+    plans = [P.Plan(grid, prob["sampling"], prob["mc"], prob["idx"], prob["perm"]) for _ in range(K)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(K)]   # default priority
+    xs = [torch.from_numpy(vessel_phantom((n, n, n), 8, 24, 1.0, 4.0, 1 + k).astype(np.float32)).to(dev)
+          for k in range(K)]
+    fk = [torch.empty(plans[0].data_shape, dtype=torch.float32, device=dev) for _ in range(K)]
+    gk = [torch.empty(plans[0].vol_shape, dtype=torch.float32, device=dev) for _ in range(K)]
+
+    def run_all():
+        for k in range(K):
+            with torch.cuda.stream(streams[k]):
+                P.pat_forward(plans[k], xs[k], fk[k])
+                P.pat_adjoint(plans[k], fk[k], gk[k])
+
+    torch.cuda.synchronize()
+    run_all()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        run_all()
+    torch.cuda.synchronize()
+    agg = reps * K / (time.perf_counter() - t)
+    ws = sum(pl.workspace.numel() for pl in plans)
+    for pl in plans:
+        pl.close()
+    return agg, ws
+
+
+def cpu_baseline(n, nt, p0, smp_kind, mc, idx, perm, steps, workers):
     """The FP64 oracle on the host, `steps` forward and `steps` adjoint time steps, scaled to one pair."""
     import oracle
     from oracle.sampling import Sampling, apply_c, apply_ct
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    cores = max(1, min(cores, os.cpu_count() or 1))
     g = oracle.Grid(n, n, n, dx=100e-6, c0=1500.0, dt=20e-9, nt=steps + 1, pml_size=8)
-    op = oracle.WaveOperator(g, workers=cores)
+    op = oracle.WaveOperator(g, workers=workers)
     smp = Sampling(smp_kind, mc, idx=idx, perm=perm) if smp_kind != "full" else Sampling.full(n * n)
     t0 = time.perf_counter()
     f = apply_c(op.forward_planes(p0), smp)
     op.adjoint_planes(apply_ct(f, smp, n, n))
     dt = time.perf_counter() - t0
     pair_s = dt * (nt - 1) / steps
-    return {"value": 1.0 / pair_s, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / pair_s, "unit": "pairs/s", "cores": workers, "kind": "oracle",
             "sample": f"{steps} forward + {steps} adjoint time steps of the FP64 NumPy oracle at {n}^3 "
-                      f"({dt:.1f} s), scaled by {nt - 1}/{steps} to one pair"}
+                      f"({dt:.1f} s, {workers} FFT thread(s)), scaled by {nt - 1}/{steps} to one pair (extrapolated)"}
 
 
 def main():
@@ -99,14 +208,12 @@ def main():
     ap.add_argument("--nt", type=int, default=740)
     ap.add_argument("--n-prox", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps-1", type=int, default=3, help="time steps of the one-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scheme", choices=["line", "slab"], default="line",
-                    help="propagator implementation (line needs FP64 butterflies)")
-    ap.add_argument("--fft-precision", type=int, choices=[32, 64], default=64,
-                    help="arithmetic of the FFT butterflies (storage is FP32 either way)")
-    ap.add_argument("--concurrent", type=int, default=2,
-                    help="also time this many independent problems at once, one plan and stream each "
-                         "(reported apart from the value; 0 or 1: skip)")
+    ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--other-sampling", type=int, default=1, help="also time the other sampling mode (0: skip)")
+    ap.add_argument("--concurrent", default="2,4",
+                    help="comma-separated counts of independent problems timed at once ('' or 0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -117,71 +224,35 @@ def main():
 
     import torch
     from paper_1605_00133_amd import pat as P
-    from synthetic import gaussian_data, gaussian_volume, vessel_phantom
+    from paper_1605_00133_amd.workload import paper_problem, tv_bregman_curve
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    dev = torch.device("cuda:0")
-    n, nt, pml = args.n, args.nt, 8
-    npix, mc = n * n, (n * n) // 8
-    if args.sampling == "points":
-        idx, perm = P.pat_make_rsp_mask(npix, mc, 2), None
-    else:
-        perm, idx = P.pat_make_shd_pattern(npix, mc, 4)
-    grid = P.make_grid(n, n, n, 100e-6, 1500.0, 20e-9, nt, pml)
-    plan = P.Plan(grid, args.sampling, mc, idx, perm)
-    plan.set_fft_precision(args.fft_precision)
-    if args.fft_precision == 64:
-        plan.set_scheme(args.scheme)
-    log(f"plan {n}^3 nt={nt} {args.sampling} mc={mc}: workspace {plan.workspace.numel() / 2**20:.0f} MiB")
+    n, nt = args.n, args.nt
+    prob = paper_problem(args.sampling, n, nt)
+    if prob["lam_br"] is None:   # a grid other than the frozen workload's: the rule of thumb
+        prob["lam_tv"] = 6.3e-4 * prob["sigma"] * np.sqrt(prob["plan"].data_shape[0] * prob["mc"])
+        prob["lam_br"] = 10.0 * prob["lam_tv"]
+    plan, mc = prob["plan"], prob["mc"]
+    log(f"plan {n}^3 nt={nt} {args.sampling} mc={mc}: workspace {plan.workspace.numel() / 2**20:.0f} MiB; "
+        f"L = {prob['L']:.4e}, sigma = {prob['sigma']:.3e}, lambda_TV+ = {prob['lam_tv']:.4e}, "
+        f"lambda_Br = {prob['lam_br']:.4e}")
 
-    p0_h = vessel_phantom((n, n, n), pml, 24, 1.0, 4.0, 1)
-    p0 = torch.from_numpy(p0_h.astype(np.float32)).to(dev)
-    f = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
-    P.pat_forward(plan, p0, f)
-    torch.cuda.synchronize()
-    sigma = 0.01 * float(f.abs().max())
-    f += sigma * torch.from_numpy(gaussian_data(plan.data_shape, 3).astype(np.float32)).to(dev)
-    x0 = torch.from_numpy(gaussian_volume(plan.vol_shape, 8).astype(np.float32)).to(dev)
-    L = P.pat_power_iteration(plan, x0, 10)
-    lam = 2e-3 * sigma * np.sqrt(nt * mc) / 1.0
-    log(f"L = {L:.4e}, sigma = {sigma:.3e}, lambda = {lam:.3e}")
-    p = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
-
-    def run(iters):
-        return P.pat_reconstruct(plan, f, p, lam, L, n_outer=1, n_inner=iters, n_prox=args.n_prox,
-                                 bc="dirichlet", restart=True, p_ref=p0)
-
-    if args.warmup > 0:
-        run(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = run(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # ---- the timed region: K FISTA iterations -------------------------------------------
+    pairs, elapsed, out = fista_rate(P, torch, prob, args.steps, args.warmup, args.n_prox)
     flags = out["flags"]
-    n_fwd = args.steps + int(flags.sum())
-    n_adj = args.steps + int((flags > 0).sum())
-    pairs = 0.5 * (n_fwd + n_adj)
-    elapsed = t1 - t0
     log(f"timed: {args.steps} FISTA steps in {elapsed:.3f} s, {pairs} pairs, restarts {int((flags > 0).sum())}, "
-        f"final PSNR {out['psnr'][-1]:.2f} dB")
+        f"PSNR after them {out['psnr'][-1]:.2f} dB")
 
-    # operator-only pairs (A then A^T, nothing else)
+    op_pairs_s = operator_rate(P, torch, prob)
+
+    # ---- live per-kernel timing of one pair with HIP events on the plan's stream ----------
+    dev = prob["f"].device
     g = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     ftmp = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(3):
-        P.pat_forward(plan, p0, ftmp)
-        P.pat_adjoint(plan, ftmp, g)
-    torch.cuda.synchronize()
-    op_pairs_s = 3 / (time.perf_counter() - t2)
-
-    # live per-kernel timing of one pair with HIP events on the plan's stream
     P.pat_profile_begin(plan, -2, 8 * nt + 64)
-    P.pat_forward(plan, p0, ftmp)
+    P.pat_forward(plan, prob["p0"], ftmp)
     P.pat_adjoint(plan, ftmp, g)
     tot_ms, launches = P.pat_profile_end(plan)
     kernels = {}
@@ -198,71 +269,91 @@ def main():
     dk = kernels[dom]
     src_hash = kernel_source_hash()
     traffic = measured_traffic(dom, src_hash)
+    R, Cb = 4.0 * n ** 3, 8.0 * n * n * (n // 2 + 1)
+    survey_bytes = 20 * Cb + 12 * R     # one time step at two global passes per 3D FFT
     roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"]}
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"],
+                "frac_of_3d_fft_step_bytes": round(survey_bytes / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    # independent problems (other phantoms, parameter sweeps, frames of a 4D scan)
-    # overlap on the GPU when each has its own plan and stream: aggregate rate
-    concurrent = None
-    if args.concurrent > 1:
-        K = args.concurrent
-        plans = [plan] + [P.Plan(grid, args.sampling, mc, idx, perm) for _ in range(K - 1)]
-        for q in plans[1:]:
-            q.set_fft_precision(args.fft_precision)
-            if args.fft_precision == 64:
-                q.set_scheme(args.scheme)
-        streams = [torch.cuda.Stream(device=dev) for _ in range(K)]   # default priority
-        xs = [torch.from_numpy(vessel_phantom((n, n, n), pml, 24, 1.0, 4.0, 1 + k).astype(np.float32)).to(dev)
-              for k in range(K)]
-        fk = [torch.empty(plan.data_shape, dtype=torch.float32, device=dev) for _ in range(K)]
-        gk = [torch.empty(plan.vol_shape, dtype=torch.float32, device=dev) for _ in range(K)]
+    err = fp64_error(P, torch, prob)
+    if err:
+        log("error vs FP64 oracle samples: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
 
-        def run_all():
-            for k in range(K):
-                with torch.cuda.stream(streams[k]):
-                    P.pat_forward(plans[k], xs[k], fk[k])
-                    P.pat_adjoint(plans[k], fk[k], gk[k])
+    # ---- the other sampling mode --------------------------------------------------------------
+    other = None
+    if args.other_sampling:
+        kind = "hadamard" if args.sampling == "points" else "points"
+        prob2 = paper_problem(kind, n, nt)
+        if prob2["lam_br"] is None:
+            prob2["lam_tv"] = 6.3e-4 * prob2["sigma"] * np.sqrt(prob2["plan"].data_shape[0] * prob2["mc"])
+            prob2["lam_br"] = 10.0 * prob2["lam_tv"]
+        pr2, el2, _ = fista_rate(P, torch, prob2, max(2, args.steps // 2), 1, args.n_prox)
+        other = {"sampling": kind, "fista_pairs_per_s": round(pr2 / el2, 4),
+                 "operator_pairs_per_s": round(operator_rate(P, torch, prob2), 4),
+                 "fp64_error": fp64_error(P, torch, prob2), "lam_tv": prob2["lam_tv"]}
+        log(f"{kind}: {other['fista_pairs_per_s']:.2f} pairs/s in FISTA, {other['operator_pairs_per_s']:.2f} "
+            f"operator pairs/s")
+        prob2["plan"].close()
 
-        torch.cuda.synchronize()
-        run_all()
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        for _ in range(2):
-            run_all()
-        torch.cuda.synchronize()
-        agg = 2 * K / (time.perf_counter() - t3)
-        concurrent = {"problems": K, "aggregate_operator_pairs_per_s": round(agg, 4),
-                      "vs_single": round(agg / op_pairs_s, 3),
-                      "note": f"independent {n}^3 problems, one plan and stream each; not the value"}
-        log(f"concurrent: {K} problems, {agg:.2f} operator pairs/s aggregate ({agg / op_pairs_s:.2f}x one)")
-        for q in plans[1:]:
-            q.close()
+    # ---- independent problems at once (above the last-level cache at 4) -----------------------
+    concurrent = []
+    for K in [int(c) for c in str(args.concurrent).split(",") if c.strip() and int(c) > 1]:
+        agg, ws = concurrent_rate(P, torch, prob, K)
+        concurrent.append({"problems": K, "aggregate_operator_pairs_per_s": round(agg, 4),
+                           "vs_single": round(agg / op_pairs_s, 3), "workspace_bytes": int(ws),
+                           "aggregate_alg_GBps": round(agg * 2 * (nt - 1) * dk["alg_bytes"] / 1e9, 1)})
+        log(f"concurrent: {K} problems, {agg:.2f} operator pairs/s aggregate ({agg / op_pairs_s:.2f}x one), "
+            f"workspaces {ws / 2**20:.0f} MiB")
+
+    # ---- time to target PSNR: plain TV+Br, and the learned iteration if trained -----------------
+    ttt = None
+    if not args.no_time_to_target:
+        c = tv_bregman_curve(prob, n_prox=args.n_prox)
+        ttt = {"tv_bregman": {k: v for k, v in c.items() if k not in ("p", "psnr", "t_ms")}}
+        ttt["tv_bregman"]["psnr_every_10"] = [round(float(x), 3) for x in c["psnr"][9::10]]
+        ttt["tv_bregman"]["t_ms_every_10"] = [round(float(x), 1) for x in c["t_ms"][9::10]]
+        log(f"TV+Br 5x50: final {c['final_psnr_db']:.2f} dB after {c['total_ms'] / 1e3:.2f} s; within 0.5 dB "
+            f"({c['target_psnr_db']:.2f} dB) at {c['t_target_ms']:.0f} ms (iteration {c['target_iteration']})")
+        try:
+            from paper_1605_00133_amd.learned_unet import bench_learned
+            ttt["learned"] = bench_learned(prob, c, log=log)
+        except (ImportError, FileNotFoundError) as e:
+            ttt["learned"] = None
+            log(f"learned: not run ({e})")
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle {args.cpu_steps}+{args.cpu_steps} steps at {n}^3 ...")
-        cpu = cpu_baseline(n, nt, p0_h, args.sampling, mc, np.asarray(idx), None if perm is None else np.asarray(perm),
-                           args.cpu_steps)
+        import oracle.operator as oop
+        cores = oop._workers()
+        log(f"cpu baseline: oracle {args.cpu_steps}+{args.cpu_steps} steps at {n}^3 on {cores} threads, "
+            f"{args.cpu_steps_1}+{args.cpu_steps_1} on one ...")
+        idx, perm = np.asarray(prob["idx"]), None if prob["perm"] is None else np.asarray(prob["perm"])
+        cpu = cpu_baseline(n, nt, prob["p0_host"], args.sampling, mc, idx, perm, args.cpu_steps, cores)
+        one = cpu_baseline(n, nt, prob["p0_host"], args.sampling, mc, idx, perm, args.cpu_steps_1, 1)
+        cpu["single_thread"] = {"value": one["value"], "unit": "pairs/s", "cores": 1, "sample": one["sample"]}
 
     res = {
         "metric": METRIC, "value": round(pairs / elapsed, 4), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "fft_arithmetic": f"f{args.fft_precision}",
-        "scheme": args.scheme if args.fft_precision == 64 else "slab",
+        "fft_arithmetic": "f64", "scheme": "line",
         "data": "synthetic (random vessel phantom, seeded mask, 1% Gaussian noise)",
         "config": {"workload": f"{n}^3 grid incl. 8-cell PML, Nt={nt}, {args.sampling} sampling mc={mc}, "
-                               f"one TV FISTA iteration per step ({args.n_prox} PDHG, restart on) inside TV+Br",
+                               f"one FISTA iteration per step ({args.n_prox} PDHG, restart on) of the first "
+                               f"TV+Br outer step, lambda_Br = 10 lambda_TV+ (discrepancy principle)",
                    "grid": n, "nt": nt, "sampling": args.sampling, "mc": mc, "n_prox": args.n_prox,
-                   "parallelism": "single GPU"},
+                   "lambda_tv": prob["lam_tv"], "lambda_br": prob["lam_br"], "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "operator_pairs_per_s": round(op_pairs_s, 4),
+        "fp64_error": err,
+        "other_sampling": other,
         "concurrent": concurrent,
+        "time_to_target": ttt,
         "kernels": kernels,
         "kernel_source_hash": src_hash,
-        "final_psnr_db": round(float(out["psnr"][-1]), 3),
+        "psnr_after_timed_steps_db": round(float(out["psnr"][-1]), 3),
     }
     print(json.dumps(res), flush=True)
 

@@ -9,7 +9,10 @@ paper   : 128^3 grid, same spacing/speed/CFL, Nt = 740, 128x128 sensor plane
           (the Tumor1/2 grid and sample count of Table 2); 24 vessels of
           radius 1-4 voxels; random 12.5 % single points (2048 of 16384) or
           2048 scrambled +-1 Hadamard patterns; 1 % noise; TV + Bregman,
-          5 outer x 50 inner FISTA iterations.
+          5 outer x 50 inner FISTA iterations. lam_tv: the TV+ weight per
+          sampling mode, chosen once by the discrepancy principle (kappa = 1.25
+          within 0.01; `python -m paper_1605_00133_amd.workload --calibrate`)
+          and frozen here; TV+Br uses br_factor * lam_tv.
 """
 
 CONFIGS = {
@@ -21,7 +24,8 @@ CONFIGS = {
                   n_vessels=24, r_min=1.0, r_max=4.0, phantom_seed=1,
                   sampling="points", mc=2048, mask_seed=2, hadamard_seed=4,
                   noise_seed=3, noise_rel=0.01,
-                  lam=None, n_outer=5, n_inner=50, n_prox=50),
+                  lam=None, lam_tv={"points": 2.7730e-3, "hadamard": 1.6518e-3}, br_factor=10.0,
+                  n_outer=5, n_inner=50, n_prox=50),
 }
 
 

@@ -87,6 +87,42 @@ pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw
                                       int32_t c_in, int32_t c_out, int32_t nz, int32_t ny, int32_t nx,
                                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* Resampling layers between the levels of the network. Tensors are float32
+ * [channels][nz][ny][nx] with channels = batch * channels; the coarse voxel
+ * (z, y, x) covers the fine voxels (2z + a, 2y + b, 2x + c), a, b, c in {0, 1}.
+ * pat_pool2_*: (nz, ny, nx) is the fine grid (even sizes; the tensor read in
+ * pairs, x of pool2_forward and dy of upsample2_backward, 8-byte
+ * aligned); forward y = mean of the 8 children, backward dx = dy(parent) / 8.
+ * pat_upsample2_*: (nz, ny, nx) is the coarse grid; forward y(child) = x,
+ * backward dx = sum of dy over the 8 children. Errors: PAT_ERR_INVALID for
+ * sizes, null pointers or alignment. */
+pat_status pat_pool2_forward(const float* x, float* y, int64_t channels, int32_t nz, int32_t ny, int32_t nx,
+                             void* stream);
+pat_status pat_pool2_backward(const float* dy, float* dx, int64_t channels, int32_t nz, int32_t ny, int32_t nx,
+                              void* stream);
+pat_status pat_upsample2_forward(const float* x, float* y, int64_t channels, int32_t nz, int32_t ny, int32_t nx,
+                                 void* stream);
+pat_status pat_upsample2_backward(const float* dy, float* dx, int64_t channels, int32_t nz, int32_t ny, int32_t nx,
+                                  void* stream);
+
+/* y = a + b (b may be NULL: y = a), then max(y, 0) if relu != 0; n elements;
+ * y may alias a or b. */
+pat_status pat_add_act(const float* a, const float* b, float* y, int64_t n, int32_t relu, void* stream);
+
+/* out = alpha x + beta y (y may be NULL: out = alpha x), then max(out, 0) if
+ * clamp0 != 0; out may alias x or y. */
+pat_status pat_axpby(const float* x, const float* y, float* out, int64_t n, float alpha, float beta, int32_t clamp0,
+                     void* stream);
+
+/* Squared-error loss of a against the target t over n elements:
+ * *loss = mean((a - t)^2) as an FP64 device scalar (block partials summed in a
+ * fixed order), and, if grad is not NULL, grad = 2 (a - t) / n, set to 0 where
+ * a <= 0 when mask0 != 0 (the gradient through an output clamp max(0, .)).
+ * workspace: device, >= pat_mse_workspace_bytes(). */
+size_t pat_mse_workspace_bytes(void);
+pat_status pat_mse(const float* a, const float* t, float* grad, int64_t n, int32_t mask0, double* loss,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
 /* grad[i] = 0 where y[i] <= 0 (or NaN), in place: the ReLU's backward given its output y. */
 pat_status pat_relu_backward(const float* y, float* grad, int64_t n, void* stream);
 

@@ -71,3 +71,35 @@ def adam_step(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1 - beta1 ** step)
     vhat = v / (1 - beta2 ** step)
     return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def pool2(x):
+    """2x2x2 average pooling over the last three axes (even sizes): the mean of the 8 children."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[:-3] + tuple(s // 2 for s in x.shape[-3:]))
+    for a in range(2):
+        for b in range(2):
+            for c in range(2):
+                out += x[..., a::2, b::2, c::2]
+    return out / 8.0
+
+
+def upsample2(x):
+    """Nearest-neighbour x2 upsampling over the last three axes: every child takes its parent's value."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[:-3] + tuple(2 * s for s in x.shape[-3:]))
+    for a in range(2):
+        for b in range(2):
+            for c in range(2):
+                out[..., a::2, b::2, c::2] = x
+    return out
+
+
+def pool2_backward(dy):
+    """Adjoint of pool2: each child receives its parent's value / 8."""
+    return upsample2(dy) / 8.0
+
+
+def upsample2_backward(dy):
+    """Adjoint of upsample2: the sum over the 8 children."""
+    return 8.0 * pool2(dy)

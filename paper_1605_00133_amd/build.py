@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpat.so")
 
-SOURCES = ["wave_kernels.hip", "line_kernels.hip", "sample_kernels.hip", "vec_kernels.hip", "conv_kernels.hip", "pat_api.cpp",
+SOURCES = ["wave_kernels.hip", "line_kernels.hip", "sample_kernels.hip", "vec_kernels.hip", "conv_kernels.hip", "nn_ops.hip", "pat_api.cpp",
            "host_rng.cpp"]
 
 ARCH = "gfx950"

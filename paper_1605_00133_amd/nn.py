@@ -24,6 +24,14 @@ SIGNATURES = {
     "pat_conv3d_backward_weight_workspace_bytes": (C.c_size_t, [_I, _I, _I, _I, _I, _I]),
     "pat_conv3d_backward_weight": (C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]),
     "pat_relu_backward": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "pat_pool2_forward": (C.c_int, [_P, _P, C.c_int64, _I, _I, _I, _P]),
+    "pat_pool2_backward": (C.c_int, [_P, _P, C.c_int64, _I, _I, _I, _P]),
+    "pat_upsample2_forward": (C.c_int, [_P, _P, C.c_int64, _I, _I, _I, _P]),
+    "pat_upsample2_backward": (C.c_int, [_P, _P, C.c_int64, _I, _I, _I, _P]),
+    "pat_add_act": (C.c_int, [_P, _P, _P, C.c_int64, _I, _P]),
+    "pat_axpby": (C.c_int, [_P, _P, _P, C.c_int64, C.c_float, C.c_float, _I, _P]),
+    "pat_mse_workspace_bytes": (C.c_size_t, []),
+    "pat_mse": (C.c_int, [_P, _P, _P, C.c_int64, _I, _P, _P, C.c_size_t, _P]),
     "pat_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _I, _P]),
 }
 
@@ -147,6 +155,75 @@ def adam_step_(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         _ptr(t, n, w.shape, w.device)
     P._check(lib().pat_adam_step(_ptr(w, "w"), _ptr(g, "g"), _ptr(m, "m"), _ptr(v, "v"), w.numel(), float(lr),
                                  float(beta1), float(beta2), float(eps), int(step), _stream(w)))
+
+
+def _vol(t, name):
+    if t.dim() != 5:
+        raise ValueError(f"{name} must be [B, C, nz, ny, nx]")
+    return int(t.shape[0]) * int(t.shape[1]), tuple(int(s) for s in t.shape[2:])
+
+
+def pool2(x):
+    """2x2x2 average pooling: [B, C, nz, ny, nx] (even sizes) -> [B, C, nz/2, ny/2, nx/2]."""
+    ch, (nz, ny, nx) = _vol(x, "x")
+    y = torch.empty(x.shape[:2] + (nz // 2, ny // 2, nx // 2), dtype=torch.float32, device=x.device)
+    P._check(lib().pat_pool2_forward(_ptr(x, "x"), _ptr(y, "y"), ch, nz, ny, nx, _stream(x)))
+    return y
+
+
+def pool2_backward(dy):
+    """Adjoint of pool2: [B, C, n/2 ...] -> [B, C, n ...], each child dy(parent) / 8."""
+    ch, (nz, ny, nx) = _vol(dy, "dy")
+    dx = torch.empty(dy.shape[:2] + (2 * nz, 2 * ny, 2 * nx), dtype=torch.float32, device=dy.device)
+    P._check(lib().pat_pool2_backward(_ptr(dy, "dy"), _ptr(dx, "dx"), ch, 2 * nz, 2 * ny, 2 * nx, _stream(dy)))
+    return dx
+
+
+def upsample2(x):
+    """Nearest-neighbour x2 upsampling: [B, C, nz, ny, nx] -> [B, C, 2nz, 2ny, 2nx]."""
+    ch, (nz, ny, nx) = _vol(x, "x")
+    y = torch.empty(x.shape[:2] + (2 * nz, 2 * ny, 2 * nx), dtype=torch.float32, device=x.device)
+    P._check(lib().pat_upsample2_forward(_ptr(x, "x"), _ptr(y, "y"), ch, nz, ny, nx, _stream(x)))
+    return y
+
+
+def upsample2_backward(dy):
+    """Adjoint of upsample2: the sum over the 8 children, [B, C, 2n ...] -> [B, C, n ...]."""
+    ch, (nz, ny, nx) = _vol(dy, "dy")
+    dx = torch.empty(dy.shape[:2] + (nz // 2, ny // 2, nx // 2), dtype=torch.float32, device=dy.device)
+    P._check(lib().pat_upsample2_backward(_ptr(dy, "dy"), _ptr(dx, "dx"), ch, nz // 2, ny // 2, nx // 2,
+                                          _stream(dy)))
+    return dx
+
+
+def add_act(a, b=None, relu=False, out=None):
+    """act(a + b) (b may be None); out may be a or b (in place)."""
+    y = torch.empty_like(a) if out is None else out
+    bp = None if b is None else _ptr(b, "b", a.shape, a.device)
+    P._check(lib().pat_add_act(_ptr(a, "a"), bp, _ptr(y, "y", a.shape, a.device), a.numel(), 1 if relu else 0,
+                               _stream(a)))
+    return y
+
+
+def axpby(x, y=None, alpha=1.0, beta=1.0, clamp0=False, out=None):
+    """alpha x + beta y (y may be None), optionally max(., 0); out may be x or y (in place)."""
+    o = torch.empty_like(x) if out is None else out
+    yp = None if y is None else _ptr(y, "y", x.shape, x.device)
+    P._check(lib().pat_axpby(_ptr(x, "x"), yp, _ptr(o, "out", x.shape, x.device), x.numel(), float(alpha),
+                             float(beta), 1 if clamp0 else 0, _stream(x)))
+    return o
+
+
+def mse(a, t, grad=None, mask0=False):
+    """Mean squared error of a against t as a device FP64 scalar tensor; fills `grad` (if given)
+    with 2 (a - t) / n, zero where a <= 0 when mask0."""
+    loss = torch.empty((), dtype=torch.float64, device=a.device)
+    nbytes = lib().pat_mse_workspace_bytes()
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=a.device)
+    gp = None if grad is None else _ptr(grad, "grad", a.shape, a.device)
+    P._check(lib().pat_mse(_ptr(a, "a"), _ptr(t, "t", a.shape, a.device), gp, a.numel(), 1 if mask0 else 0,
+                           C.c_void_p(loss.data_ptr()), C.c_void_p(ws.data_ptr()), nbytes, _stream(a)))
+    return loss
 
 
 class _Conv3d(torch.autograd.Function):

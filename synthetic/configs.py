@@ -12,7 +12,9 @@ paper   : 128^3 grid, same spacing/speed/CFL, Nt = 740, 128x128 sensor plane
           5 outer x 50 inner FISTA iterations. lam_tv: the TV+ weight per
           sampling mode, chosen once by the discrepancy principle (kappa = 1.25
           within 0.01; `python -m paper_1605_00133_amd.workload --calibrate`)
-          and frozen here; TV+Br uses br_factor * lam_tv.
+          and frozen here; TV+Br uses br_factor * lam_tv. lam_tv_rel = lam_tv /
+          (sigma sqrt(Nt M_c)) of the same calibration, for other phantoms of
+          the workload (their own noise level sigma).
 """
 
 CONFIGS = {
@@ -24,7 +26,8 @@ CONFIGS = {
                   n_vessels=24, r_min=1.0, r_max=4.0, phantom_seed=1,
                   sampling="points", mc=2048, mask_seed=2, hadamard_seed=4,
                   noise_seed=3, noise_rel=0.01,
-                  lam=None, lam_tv={"points": 2.7730e-3, "hadamard": 1.6518e-3}, br_factor=10.0,
+                  lam=None, lam_tv={"points": 2.7730e-3, "hadamard": 1.6518e-3},
+                  lam_tv_rel={"points": 6.3342e-4, "hadamard": 5.5343e-4}, br_factor=10.0,
                   n_outer=5, n_inner=50, n_prox=50),
 }
 

@@ -34,7 +34,7 @@ def test_library_exports_every_nn_function():
     from paper_1605_00133_amd import nn
     lib = nn.lib()
     names = declared_functions(NN_HEADER)
-    assert len(names) == 8
+    assert len(names) == 16
     for n in names:
         assert hasattr(lib, n), f"{n} declared in include/pat_nn.h but not exported"
     assert set(names) == set(nn.SIGNATURES), "nn binding and header disagree"

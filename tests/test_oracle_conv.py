@@ -91,3 +91,82 @@ def test_adam_first_step_moves_by_lr_times_sign():
     w, m, v = adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.1, eps=1e-12)
     assert np.allclose(w, -0.1 * np.sign(g), rtol=1e-9)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_pool2_and_upsample2_brute_force_and_adjoints():
+    from oracle.conv import pool2, pool2_backward, upsample2, upsample2_backward
+    x = _rng(20).standard_normal((2, 3, 4, 6, 8))
+    ref = np.zeros((2, 3, 2, 3, 4))
+    for i in np.ndindex(ref.shape):
+        b, c, z, y, w = i
+        ref[i] = x[b, c, 2 * z:2 * z + 2, 2 * y:2 * y + 2, 2 * w:2 * w + 2].mean()
+    assert np.allclose(pool2(x), ref, rtol=0, atol=1e-15)
+    u = upsample2(ref)
+    for i in np.ndindex(u.shape):
+        b, c, z, y, w = i
+        assert u[i] == ref[b, c, z // 2, y // 2, w // 2]
+    assert np.allclose(pool2(upsample2(ref)), ref, rtol=0, atol=1e-15)   # pooling undoes upsampling
+    yc = _rng(21).standard_normal(ref.shape)
+    yf = _rng(22).standard_normal(x.shape)
+    assert abs(np.vdot(pool2(x), yc) - np.vdot(x, pool2_backward(yc))) < 1e-12
+    assert abs(np.vdot(upsample2(yc), yf) - np.vdot(yc, upsample2_backward(yf))) < 1e-12
+
+
+def _small_unet(widths=(2, 3, 4), seed=30):
+    from oracle.unet import layer_channels
+    r = _rng(seed)
+    return {k: (0.15 * r.standard_normal((co, ci, 3, 3, 3)), 0.1 * r.standard_normal(co))
+            for k, (ci, co) in layer_channels(widths).items()}
+
+
+def test_unet_oracle_forward_is_the_composition_of_the_layer_oracle():
+    """The torch U-Net (avg_pool3d, nearest interpolate, conv3d) against the plain layer oracle."""
+    pytest.importorskip("torch")
+    import torch
+    from oracle.conv import pool2, upsample2
+    from oracle.unet import net
+    prm = _small_unet()
+    x = _rng(31).standard_normal((2, 2, 8, 8, 8))
+    c = lambda t, k, relu=True: conv3d(t, prm[k][0], prm[k][1], relu=relu)
+    a2 = c(c(x, "c1"), "c2")
+    a4 = c(c(pool2(a2), "c3"), "c4")
+    a6 = c(c(pool2(a4), "c5"), "c6")
+    a7 = np.maximum(c(upsample2(a6), "c7", False) + a4, 0)
+    a8 = c(a7, "c8")
+    a9 = np.maximum(c(upsample2(a8), "c9", False) + a2, 0)
+    ref = c(c(a9, "c10"), "c11", False)
+    tp = {k: (torch.from_numpy(w), torch.from_numpy(b)) for k, (w, b) in prm.items()}
+    got = net(tp, torch.from_numpy(x)).numpy()
+    assert np.abs(ref).max() > 0.1
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_unet_oracle_gradients_match_central_differences():
+    pytest.importorskip("torch")
+    from oracle.unet import loss_and_grads
+    prm = _small_unet(seed=32)
+    r = _rng(33)
+    p = np.abs(r.standard_normal((1, 1, 8, 8, 8)))
+    z = r.standard_normal((1, 1, 8, 8, 8)) + 1.0
+    t = np.abs(r.standard_normal((1, 1, 8, 8, 8)))
+    _, _, g = loss_and_grads(prm, p, z, t)
+    eps = 1e-6
+    for name, idx in [("c1", (0, 1, 2, 1, 0)), ("c6", (3, 2, 1, 1, 1)), ("c9", (1, 2, 0, 2, 2)), ("c11", (0, 0, 1, 1, 1))]:
+        w = prm[name][0]
+        old = w[idx]
+        w[idx] = old + eps
+        lp, _, _ = loss_and_grads(prm, p, z, t)
+        w[idx] = old - eps
+        lm, _, _ = loss_and_grads(prm, p, z, t)
+        w[idx] = old
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[name][0][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, fd, g[name][0][idx])
+    bfd = []
+    b = prm["c7"][1]
+    b[1] += eps
+    lp, _, _ = loss_and_grads(prm, p, z, t)
+    b[1] -= 2 * eps
+    lm, _, _ = loss_and_grads(prm, p, z, t)
+    b[1] += eps
+    bfd = (lp - lm) / (2 * eps)
+    assert abs(bfd - g["c7"][1][1]) <= 1e-6 * max(1.0, abs(bfd))

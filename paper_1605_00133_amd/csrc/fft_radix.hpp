@@ -1,8 +1,9 @@
 // Small DFTs in registers and the two-stage split of the propagator's FFTs, for gfx950.
 //
-// The wave propagator needs power-of-two transforms of lengths 8..128 along
-// each axis of a 3D grid. A length-L transform is split as L = R0 * M
-// (R0 = 16 for L = 16, 128; 8 for L = 8, 32, 64; M = L / R0, M = 1 for L <= 16):
+// The wave propagator needs transforms of lengths 8..128 along each axis of a
+// 3D grid (powers of two, and 48 = 12 * 4, 96 = 12 * 8 for 96^3 grids). A
+// length-L transform is split as L = R0 * M (R0 = 16 for L = 16, 128; 12 for
+// L = 48, 96; 8 for L = 8, 32, 64; M = L / R0, M = 1 for L <= 16):
 //
 //  * forward stage 0 (decimation in frequency): for every n1 < M the R0 values
 //    x[n1 + M m], m < R0, go through an R0-point DFT and are multiplied by
@@ -31,7 +32,8 @@ __host__ __device__ constexpr int fft_nstages(int L) { return L <= 16 ? 1 : 2; }
 
 __host__ __device__ constexpr int fft_radix(int L, int s) {
   return L == 4 ? 4 : L == 8 ? 8 : L == 16 ? 16 :
-         L == 32 ? (s == 0 ? 8 : 4) : L == 64 ? 8 : L == 128 ? (s == 0 ? 16 : 8) : 16;
+         L == 32 ? (s == 0 ? 8 : 4) : L == 64 ? 8 : L == 128 ? (s == 0 ? 16 : 8) :
+         L == 48 ? (s == 0 ? 12 : 4) : L == 96 ? (s == 0 ? 12 : 8) : 16;
 }
 
 // Sub-transform length entering stage s.
@@ -164,12 +166,69 @@ __device__ __forceinline__ void dft16(V* a) {
   for (int i = 0; i < 16; ++i) a[i] = b[i];
 }
 
+// 3-point DFT: X0 = a0 + t, X1,2 = (a0 - t/2) -+ i (sqrt3/2) (a1 - a2) (forward; inverse: +-), t = a1 + a2
+constexpr double kSqrt3Half = 0.86602540378443864676;   // sin(pi/3)
+
+template <bool INV, typename V>
+__device__ __forceinline__ void dft3(V& a0, V& a1, V& a2) {
+  using S = typename ScalarOf<V>::T;
+  const V t = cadd(a1, a2);
+  const V m = mkc<V>(a0.x - (S)0.5 * t.x, a0.y - (S)0.5 * t.y);
+  const V d = csub(a1, a2);
+  const V r = mul_mi<INV>(cscale(d, (S)kSqrt3Half));   // -i (sqrt3/2) d forward, +i inverse
+  a0 = cadd(a0, t);
+  a1 = cadd(m, r);
+  a2 = csub(m, r);
+}
+
+// multiply by w12^j = exp(-+ 2 pi i j / 12) for the products j = n2 k1 of dft12
+template <bool INV, typename V>
+__device__ __forceinline__ V tw12(V a, int j) {
+  using S = typename ScalarOf<V>::T;
+  S c, s;
+  switch (j) {
+    case 1: c = (S)kSqrt3Half; s = (S)0.5; break;
+    case 2: c = (S)0.5; s = (S)kSqrt3Half; break;
+    case 3: c = (S)0; s = (S)1; break;
+    case 4: c = -(S)0.5; s = (S)kSqrt3Half; break;
+    case 6: c = -(S)1; s = (S)0; break;
+    default: return a;
+  }
+  const S sg = INV ? s : -s;   // exp(-+ i theta) = c -+ i s
+  return mkc<V>(a.x * c - a.y * sg, a.x * sg + a.y * c);
+}
+
+template <bool INV, typename V>
+__device__ __forceinline__ void dft12(V* a) {
+  // n = 4 n1 + n2 (n1 < 3, n2 < 4), k = k1 + 3 k2:
+  // X = sum_n2 w4^{n2 k2} [ w12^{n2 k1} sum_n1 a[4n1+n2] w3^{n1 k1} ]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft3<INV>(a[n2], a[4 + n2], a[8 + n2]);
+  // now a[4*k1 + n2] holds B[n2][k1]
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 3; ++k1) a[4 * k1 + n2] = tw12<INV>(a[4 * k1 + n2], n2 * k1);
+  V b[12];
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    V c0 = a[4 * k1 + 0], c1 = a[4 * k1 + 1], c2 = a[4 * k1 + 2], c3 = a[4 * k1 + 3];
+    dft4<INV>(c0, c1, c2, c3);
+    b[k1] = c0; b[k1 + 3] = c1; b[k1 + 6] = c2; b[k1 + 9] = c3;
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) a[i] = b[i];
+}
+
 template <int R, bool INV, typename V>
 __device__ __forceinline__ void dft_r(V* a) {
   if constexpr (R == 1) (void)a;
+  else if constexpr (R == 3) dft3<INV>(a[0], a[1], a[2]);
   else if constexpr (R == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
   else if constexpr (R == 8) dft8<INV>(a);
+  else if constexpr (R == 12) dft12<INV>(a);
   else if constexpr (R == 16) dft16<INV>(a);
+  else static_assert(R == 1 || R == 3 || R == 4 || R == 8 || R == 12 || R == 16, "radix not built");
 }
 
 // Stage-0 twiddles of butterfly n1 (< M): a[k] *= w^k (forward) or conj(w)^k

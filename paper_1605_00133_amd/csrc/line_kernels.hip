@@ -1023,6 +1023,7 @@ static const LineImpl kLineImpls[] = {
     PAT_LINE_IMPL(16),
     PAT_LINE_IMPL(32),
     PAT_LINE_IMPL(64),
+    PAT_LINE_IMPL(96),
     PAT_LINE_IMPL(128),
 };
 

@@ -1505,6 +1505,7 @@ hipError_t launch_slab_r2c(int n, const float* in, float2* out, int nb, float sc
     case 16: return slab_r2c_n<16>(in, out, nb, scale, t, st);
     case 32: return slab_r2c_n<32>(in, out, nb, scale, t, st);
     case 64: return slab_r2c_n<64>(in, out, nb, scale, t, st);
+    case 96: return slab_r2c_n<96>(in, out, nb, scale, t, st);
     case 128: return slab_r2c_n<128>(in, out, nb, scale, t, st);
     default: return hipErrorInvalidValue;
   }
@@ -1516,6 +1517,7 @@ hipError_t launch_slab_c2r(int n, const float2* in, float* out, int nb, float sc
     case 16: return slab_c2r_n<16>(in, out, nb, scale, t, st);
     case 32: return slab_c2r_n<32>(in, out, nb, scale, t, st);
     case 64: return slab_c2r_n<64>(in, out, nb, scale, t, st);
+    case 96: return slab_c2r_n<96>(in, out, nb, scale, t, st);
     case 128: return slab_c2r_n<128>(in, out, nb, scale, t, st);
     default: return hipErrorInvalidValue;
   }
@@ -1599,6 +1601,7 @@ static const WaveImpl kWaveImpls[] = {
     PAT_WAVE_IMPL(16),
     PAT_WAVE_IMPL(32),
     PAT_WAVE_IMPL(64),
+    PAT_WAVE_IMPL(96),
     PAT_WAVE_IMPL(128),
 };
 

@@ -55,8 +55,8 @@ typedef enum {
 /* Discretisation (Table 2 lists the paper's values). The FFT grid includes
  * the PML: pml_size cells on each side in x and y, and a 2*pml_size slab at
  * the top of z (z in [nz - 2 pml, nz)), so the plane z = 0 sits directly in
- * front of it. nx, ny, nz must each be one of the built sizes (16, 32, 64,
- * 128) and nt >= 1. */
+ * front of it. The grid is cubic, nx = ny = nz one of the built sizes (16, 32,
+ * 64, 96, 128; 96 uses radix-3 butterflies), and nt >= 1. */
 typedef struct {
   int32_t nx, ny, nz;
   double dx;          /* voxel size [m], isotropic */
@@ -116,7 +116,10 @@ pat_status pat_plan_set_fft_precision(pat_plan* plan, int32_t bits);
  *    time step is one launch of independent 1D lines (four transforms per
  *    line). It needs FP64 butterflies; with pat_plan_set_fft_precision(32)
  *    the slab scheme runs. Returns PAT_ERR_UNSUPPORTED when the grid has no
- *    line propagator. */
+ *    line propagator.
+ * Only the line scheme may be captured into a HIP graph: the slab scheme's
+ * hand-off flags are tagged with a per-launch count kept on the host, so its
+ * operator calls return PAT_ERR_UNSUPPORTED on a capturing stream. */
 typedef enum { PAT_SCHEME_SLAB = 0, PAT_SCHEME_LINE = 1 } pat_scheme;
 pat_status pat_plan_set_scheme(pat_plan* plan, int32_t scheme);
 
@@ -191,6 +194,18 @@ typedef struct {
  * energy. */
 pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p,
                            const pat_recon_params* params, pat_recon_report* report);
+
+/* n_iter FISTA iterations of TV+ (eq. VarReg/TV+, App. B) from p = 0 without
+ * restart, enqueued on the plan's stream with no host synchronisation and no
+ * memory copies or sets (kernels only), so that the whole call can be captured
+ * into a HIP graph; it is the arithmetic of pat_reconstruct with n_outer = 1
+ * and restart = 0, and gives the same p bit for bit. f: device [nt][mc];
+ * p: device volume (output); log: NULL or device FP64 [n_iter][2] receiving
+ * sum((C A x - f)^2) and TV(x) of each iterate (the energy is half the first
+ * plus lambda times the second). Arguments are checked on the host; nothing is
+ * read back, so non-finite values show up only in p and the log. */
+pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t n_iter,
+                             int32_t n_prox, int32_t bc, double* log);
 
 /* Thresholded PSNR of p against p_ref (eq. PSNR) over the non-PML interior with
  * z >= 1: negatives clipped, both scaled by their maximum, values < 0.1 zeroed.

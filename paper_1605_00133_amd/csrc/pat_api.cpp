@@ -99,7 +99,7 @@ pat_status validate_grid(const pat_grid* g) {
   if (!(g->pml_alpha >= 0) || !std::isfinite(g->pml_alpha))
     return set_error(PAT_ERR_INVALID, "pml_alpha must be finite and >= 0");
   if (!find_wave_impl(g->nx, g->ny, g->nz))
-    return set_error(PAT_ERR_UNSUPPORTED, "grid %dx%dx%d is not built (cubic 16, 32, 64, 128)", g->nx, g->ny, g->nz);
+    return set_error(PAT_ERR_UNSUPPORTED, "grid %dx%dx%d is not built (cubic 16, 32, 64, 96, 128)", g->nx, g->ny, g->nz);
   return PAT_OK;
 }
 
@@ -388,7 +388,20 @@ long data_n(const pat_plan* P) { return (long)P->g.nt * P->mc; }
 // ---- operator pieces used by the entry points and the solver ----------------
 bool use_line(const pat_plan* P) { return P->scheme == PAT_SCHEME_LINE && P->limpl && P->fftp == FFT_FP64; }
 
+// The slab scheme tags its hand-off flags with an epoch the host advances per
+// launch; a graph would replay stale epochs, so that scheme refuses capture.
+pat_status check_capture(const pat_plan* P) {
+  if (use_line(P)) return PAT_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(P->stream, &cs);
+  if (e != hipSuccess) return set_error(PAT_ERR_HIP, "hipStreamIsCapturing: %s", hipGetErrorString(e));
+  if (cs != hipStreamCaptureStatusNone)
+    return set_error(PAT_ERR_UNSUPPORTED, "the slab scheme cannot be captured into a graph (use the line scheme)");
+  return PAT_OK;
+}
+
 pat_status op_forward(pat_plan* P, const float* p0, float* f) {
+  PAT_TRY(check_capture(P));
   float* planes = P->kind == PAT_SAMPLE_FULL ? f : P->planes;
   const long nplane = (long)P->g.nt * P->npix;
   KernelTimer* kt = P->timer.ev ? &P->timer : nullptr;
@@ -407,6 +420,7 @@ pat_status op_forward(pat_plan* P, const float* p0, float* f) {
 }
 
 pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
+  PAT_TRY(check_capture(P));
   const float* planes = f;
   if (P->kind == PAT_SAMPLE_POINTS) {
     PAT_TRY_HIP(launch_rsp_scatter(f, P->inv, P->planes, P->npix, P->mc, P->g.nt, P->stream));
@@ -827,6 +841,54 @@ pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p, const pat_r
   }
   PAT_TRY_HIP(hipMemcpyAsync(p, xp, nv * sizeof(float), hipMemcpyDeviceToDevice, st));
   PAT_TRY_HIP(hipStreamSynchronize(st));
+  return PAT_OK;
+}
+
+pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t n_iter,
+                             int32_t n_prox, int32_t bc, double* log) {
+  PAT_TRY(check_plan(plan));
+  if (!f || !p) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: null pointer");
+  if (!(L > 0) || !std::isfinite(L)) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: L must be > 0");
+  if (!(lambda >= 0) || !std::isfinite(lambda)) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: lambda must be >= 0");
+  if (n_iter < 0 || n_prox < 0) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: iteration counts out of range");
+  if (bc != 0 && bc != 1) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: bc must be 0 or 1");
+  if (overlaps(p, vol_bytes(plan), f, data_bytes(plan)))
+    return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: f and p overlap");
+  DeviceGuard dg(plan->device);
+  hipStream_t st = plan->stream;
+  const long nv = vol_n(plan), nd = data_n(plan);
+  const double eta = 1.8 / L;
+  float *x = plan->img[IMG_X], *xp = plan->img[IMG_XPREV], *y = plan->img[IMG_Y];
+  float *g = plan->img[IMG_G], *v = plan->img[IMG_V];
+  float *rx = plan->data[DAT_RX], *rp = plan->data[DAT_RPREV], *ry = plan->data[DAT_RY];
+  float* tmp = plan->data[DAT_TMP];
+  // the same arithmetic, in the same order, as pat_reconstruct with n_outer = 1 and restart = 0,
+  // but every operand stays on the device: kernels only, no copies, no host synchronisation
+  PAT_TRY_HIP(launch_fill(xp, 0.f, nv, st));
+  PAT_TRY_HIP(launch_fill(plan->dual, 0.f, (long)n_dual(plan->g, bc), st));
+  PAT_TRY_HIP(launch_scale(f, rp, -1.f, nd, st));               // x0 = 0: r_prev = -f
+  PAT_TRY_HIP(launch_fill(y, 0.f, nv, st));
+  PAT_TRY_HIP(launch_scale(rp, ry, 1.f, nd, st));
+  double t = 1.0;
+  for (int it = 0; it < n_iter; ++it) {
+    PAT_TRY(op_adjoint(plan, ry, g));
+    PAT_TRY_HIP(launch_axpy(y, g, v, (float)(-eta), nv, st));
+    PAT_TRY(op_prox(plan, v, x, (float)(eta * lambda), n_prox, bc, plan->dual));
+    PAT_TRY(op_forward(plan, x, tmp));
+    PAT_TRY_HIP(launch_axpy(tmp, f, rx, -1.f, nd, st));
+    if (log) {
+      PAT_TRY_HIP(launch_reduce_vec(rx, nullptr, nd, 0, plan->red_partial, log + 2 * it, st));
+      PAT_TRY_HIP(launch_reduce_tv(x, plan->g.nx, plan->g.ny, plan->g.nz, bc, plan->red_partial, log + 2 * it + 1, st));
+    }
+    const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double beta = (t - 1.0) / t_next;
+    PAT_TRY_HIP(launch_extrapolate(x, xp, y, (float)beta, nv, st));
+    PAT_TRY_HIP(launch_extrapolate(rx, rp, ry, (float)beta, nd, st));
+    std::swap(x, xp);
+    std::swap(rx, rp);
+    t = t_next;
+  }
+  PAT_TRY_HIP(launch_scale(xp, p, 1.f, nv, st));
   return PAT_OK;
 }
 

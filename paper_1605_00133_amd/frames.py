@@ -107,22 +107,112 @@ def reconstruct_all(plans, fs, ps, lams, Ls, workers=None, warm=True, **kwargs):
     return outs
 
 
-def dynamic_scan(sizes=(64,), n_frames=24, iters=30, workers=4, rate=8, n_prox=50, seed=1, log=print):
-    """A dynamic (4D) scan: n_frames frames of a moving vessel phantom, each on a
-    grid drawn from `sizes` (dx = 100 um, c0 = 1500 m/s, CFL 0.3, Nt = 740 N / 128,
-    8-cell PML), with an independent random single-point mask keeping 1/rate of the
-    sensor pixels, data C A p0 + 1 % Gaussian noise, and `iters` TV+ FISTA
-    iterations per frame (lambda as for one 128^3 problem, L by power iteration on
-    the first frame of each size). The frames are reconstructed once one after
-    another on one stream and once by `workers` concurrent workers; returns a dict
-    with both rates (frames/s) and the per-frame PSNR against the true frame."""
-    import time
+class CapturedScan:
+    """Every frame's TV+ FISTA (n_iter iterations from 0, no restart) captured as ONE
+    HIP graph (torch.cuda.CUDAGraph over pat_fista_enqueue): frame k runs on branch
+    k % branches of the graph, the branches join at its end, and one replay()
+    launches the whole scan. Plans must use the line scheme (the slab scheme refuses
+    capture). Outputs ps[k] and the per-iteration logs [n_iter, 2] (sum r^2, TV) are
+    overwritten by each replay; data are read from fs[k] at replay time."""
 
+    def __init__(self, plans, fs, lams, Ls, n_iter, n_prox=50, branches=4, order=None):
+        dev = plans[0].device
+        self.plans, self.fs, self.n_iter = plans, fs, int(n_iter)
+        self.order = list(range(len(plans))) if order is None else list(order)
+        self.branches = max(1, min(int(branches), len(plans)))
+        self.ps = [torch.empty(pl.vol_shape, dtype=torch.float32, device=dev) for pl in plans]
+        self.logs = [torch.zeros((self.n_iter, 2), dtype=torch.float64, device=dev) for _ in plans]
+        self.args = [(float(lams[k]), float(Ls[k])) for k in range(len(plans))]
+        self.n_prox = int(n_prox)
+        side = [torch.cuda.Stream(device=dev) for _ in range(self.branches)]   # default priority
+
+        def enqueue_all():
+            cur = torch.cuda.current_stream(dev)
+            for s in side:
+                s.wait_stream(cur)
+            for j, k in enumerate(self.order):
+                with torch.cuda.stream(side[j % self.branches]):
+                    lam, L = self.args[k]
+                    P.pat_fista_enqueue(self.plans[k], self.fs[k], self.ps[k], lam, L, self.n_iter, self.n_prox,
+                                        "dirichlet", self.logs[k])
+            for s in side:
+                cur.wait_stream(s)
+
+        enqueue_all()                       # eager run: first launches and code loading outside the capture
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            enqueue_all()
+        for pl in plans:
+            pl.sync_stream()                # back to the caller's stream for eager use
+
+    def replay(self):
+        self.graph.replay()
+
+    def energies(self):
+        """Per frame, the energy 1/2 ||C A x - f||^2 + lambda TV(x) after each iteration (host arrays)."""
+        return [0.5 * lg[:, 0].cpu().numpy() + self.args[k][0] * lg[:, 1].cpu().numpy()
+                for k, lg in enumerate(self.logs)]
+
+
+def autotune_scan(plans, fs, lams, Ls, n_iter, n_prox=50, candidates=(1, 2, 4, 8), probe_iters=2, cache=None,
+                  log=None):
+    """Chooses the number of graph branches and the frame order (largest first, or sizes
+    interleaved) of a CapturedScan by timing replays of graphs with `probe_iters`
+    iterations; the choice is written to `cache` (a JSON path) if given. Returns
+    (choice, timings)."""
+    import json
+    import time
+    sizes = [pl.grid.nx for pl in plans]
+    largest = sorted(range(len(plans)), key=lambda k: -sizes[k])
+    inter = []
+    buckets = {}
+    for k in largest:
+        buckets.setdefault(sizes[k], []).append(k)
+    while any(buckets.values()):
+        for n in sorted(buckets, reverse=True):
+            if buckets[n]:
+                inter.append(buckets[n].pop(0))
+    timings = []
+    for order_name, order in (("largest_first", largest), ("interleaved", inter)):
+        for b in candidates:
+            if b > len(plans):
+                continue
+            scan = CapturedScan(plans, fs, lams, Ls, probe_iters, n_prox, b, order)
+            scan.replay()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(2):
+                scan.replay()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t) / 2
+            timings.append({"order": order_name, "branches": b, "ms": ms})
+            if log:
+                log(f"autotune: {order_name}, {b} branches: {ms:.1f} ms per replay of {probe_iters} iterations")
+            del scan
+    best = min(timings, key=lambda r: r["ms"])
+    choice = {"branches": best["branches"], "order": best["order"],
+              "frame_order": largest if best["order"] == "largest_first" else inter,
+              "sizes": sizes, "probe_iters": probe_iters, "n_iter": n_iter}
+    if cache:
+        with open(cache, "w") as fh:
+            json.dump({"choice": choice, "timings": timings}, fh)
+    return choice, timings
+
+
+def _scan_setup(sizes, n_frames, rate, seed, lam_rel=None):
+    """Frames of a moving vessel phantom (1 voxel per frame, 10 % amplitude pulsation), each
+    on a grid drawn from `sizes` with its own random single-point mask keeping 1/rate of the
+    plane, data C A p0 + 1 % noise, lambda = lam_rel sigma sqrt(Nt M_c) (default: the value
+    for one 128^3 problem, 2e-3) and L by power iteration on the first frame of each size.
+    Returns plans, phantoms, data, lambdas, Ls, {size: L}, the size of each frame (largest
+    frames first)."""
     import numpy as np
 
     from synthetic import gaussian_data, gaussian_volume
     from synthetic import moving_vessel_frames
 
+    lam_rel = 2e-3 if lam_rel is None else float(lam_rel)
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(seed)
     frame_n = [int(sizes[i]) for i in rng.integers(0, len(sizes), n_frames)]
@@ -148,8 +238,72 @@ def dynamic_scan(sizes=(64,), n_frames=24, iters=30, workers=4, rate=8, n_prox=5
         plans.append(plan)
         p0s.append(p0)
         fs.append(f)
-        lams.append(2e-3 * sigma * np.sqrt(nt * mc))
+        lams.append(lam_rel * sigma * np.sqrt(nt * mc))
         Ls.append(L_of[n])
+    return plans, p0s, fs, lams, Ls, L_of, [frame_n[t] for t in order]
+
+
+def captured_dynamic_scan(sizes=(64, 96, 128), n_frames=24, iters=30, rate=8, n_prox=50, seed=1, tune=True,
+                          cache=None, log=print):
+    """The dynamic (4D) scan as one HIP graph: all frames' TV+ FISTA (`iters` iterations,
+    no restart) captured once (CapturedScan, branches and order from autotune_scan) and
+    launched with one replay; against the same iterations run eagerly frame after frame
+    (pat_reconstruct, restart off: equal bit for bit). Returns rates and PSNRs."""
+    import time
+
+    import numpy as np
+
+    plans, p0s, fs, lams, Ls, L_of, frame_n = _scan_setup(sizes, n_frames, rate, seed)
+    torch.cuda.synchronize()
+    log(f"{n_frames} frames, sizes {dict((n, frame_n.count(n)) for n in sorted(set(frame_n)))}, L {L_of}")
+    if tune:
+        choice, timings = autotune_scan(plans, fs, lams, Ls, iters, n_prox, cache=cache, log=log)
+    else:
+        choice, timings = {"branches": 4, "frame_order": list(range(n_frames)), "order": "largest_first"}, []
+    scan = CapturedScan(plans, fs, lams, Ls, iters, n_prox, choice["branches"], choice["frame_order"])
+    scan.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scan.replay()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    eager = [torch.empty(pl.vol_shape, dtype=torch.float32, device=f.device) for pl, f in zip(plans, fs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, f, p, lam, L in zip(plans, fs, eager, lams, Ls):
+        P.pat_reconstruct(pl, f, p, lam, L, n_outer=1, n_inner=iters, n_prox=n_prox, bc="dirichlet", restart=False)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(scan.ps, eager))
+    psnr = [P.pat_psnr(pl, p, p0) for pl, p, p0 in zip(plans, scan.ps, p0s)]
+    log(f"graph: {t_graph:.2f} s ({n_frames / t_graph:.3f} frames/s), eager one after another: {t_eager:.2f} s "
+        f"({n_frames / t_eager:.3f} frames/s), identical {same}")
+    out = {"frames": n_frames, "sizes": sorted(set(frame_n)), "frame_sizes": frame_n, "iters": iters,
+           "n_prox": n_prox, "graph_s": t_graph, "frames_per_s_graph": n_frames / t_graph, "eager_s": t_eager,
+           "frames_per_s_eager": n_frames / t_eager, "speedup": t_eager / t_graph, "identical_to_eager": same,
+           "autotune": {k: v for k, v in choice.items() if k != "frame_order"}, "autotune_timings": timings,
+           "psnr_db_mean": float(np.mean(psnr)), "psnr_db_min": float(np.min(psnr))}
+    del scan
+    for pl in plans:
+        pl.close()
+    return out
+
+
+def dynamic_scan(sizes=(64,), n_frames=24, iters=30, workers=4, rate=8, n_prox=50, seed=1, log=print):
+    """A dynamic (4D) scan: n_frames frames of a moving vessel phantom, each on a
+    grid drawn from `sizes` (dx = 100 um, c0 = 1500 m/s, CFL 0.3, Nt = 740 N / 128,
+    8-cell PML), with an independent random single-point mask keeping 1/rate of the
+    sensor pixels, data C A p0 + 1 % Gaussian noise, and `iters` TV+ FISTA
+    iterations per frame (lambda as for one 128^3 problem, L by power iteration on
+    the first frame of each size). The frames are reconstructed once one after
+    another on one stream and once by `workers` concurrent workers; returns a dict
+    with both rates (frames/s) and the per-frame PSNR against the true frame."""
+    import time
+
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    plans, p0s, fs, lams, Ls, L_of, frame_n = _scan_setup(sizes, n_frames, rate, seed)
     torch.cuda.synchronize()
     log(f"{n_frames} frames, sizes {dict((n, frame_n.count(n)) for n in sorted(set(frame_n)))}, L {L_of}")
     kw = dict(n_outer=1, n_inner=iters, n_prox=n_prox, bc="dirichlet", restart=True)
@@ -179,14 +333,21 @@ def main(argv=None):
     import json
     import sys
     ap = argparse.ArgumentParser(description="Reconstruct the frames of a synthetic dynamic (4D) scan.")
-    ap.add_argument("--sizes", default="64", help="comma-separated grid sizes drawn per frame (16-128, powers of 2)")
+    ap.add_argument("--sizes", default="64", help="comma-separated grid sizes drawn per frame (16, 32, 64, 96, 128)")
     ap.add_argument("--frames", type=int, default=24)
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--n-prox", type=int, default=50)
+    ap.add_argument("--captured", action="store_true",
+                    help="all frames as one captured HIP graph (autotuned branches and order)")
+    ap.add_argument("--cache", default=None, help="JSON file receiving the autotuner's choice")
     a = ap.parse_args(argv)
-    out = dynamic_scan(tuple(int(s) for s in a.sizes.split(",")), a.frames, a.iters, a.workers, n_prox=a.n_prox,
-                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    sizes = tuple(int(s) for s in a.sizes.split(","))
+    lg = lambda m: print(m, file=sys.stderr, flush=True)
+    if a.captured:
+        out = captured_dynamic_scan(sizes, a.frames, a.iters, n_prox=a.n_prox, cache=a.cache, log=lg)
+    else:
+        out = dynamic_scan(sizes, a.frames, a.iters, a.workers, n_prox=a.n_prox, log=lg)
     print(json.dumps(out), flush=True)
 
 

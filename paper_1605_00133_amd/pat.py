@@ -74,6 +74,7 @@ SIGNATURES = {
     "pat_power_iteration": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
     "pat_reconstruct": (C.c_int, [_P, _P, _P, C.POINTER(pat_recon_params), C.POINTER(pat_recon_report)]),
     "pat_psnr": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
+    "pat_fista_enqueue": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P]),
     "pat_make_rsp_mask": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_int32)]),
     "pat_make_shd_pattern": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
@@ -332,3 +333,18 @@ def pat_reconstruct(plan, f, p, lam, L, n_outer=1, n_inner=10, n_prox=50, bc="di
     out["flags"] = flags[:n].copy()
     out["bregman_residual"] = breg[:n_outer].copy()
     return out
+
+
+def pat_fista_enqueue(plan, f, p, lam, L, n_iter=30, n_prox=50, bc="dirichlet", log=None):
+    """Enqueues n_iter TV+ FISTA iterations (no restart, no host synchronisation: capturable in a
+    HIP graph). log: None or a float64 device tensor [n_iter, 2] (sum r^2, TV per iteration)."""
+    plan.sync_stream()
+    lp = None
+    if log is not None:
+        t = plan.torch
+        if log.dtype != t.float64 or log.device != plan.device or not log.is_contiguous() or \
+                tuple(log.shape) != (int(n_iter), 2):
+            raise ValueError(f"log must be a contiguous float64 tensor [{n_iter}, 2] on {plan.device}")
+        lp = C.c_void_p(log.data_ptr())
+    _check(lib().pat_fista_enqueue(plan.handle, plan.check(f, plan.data_shape, "f"), plan.check(p, plan.vol_shape, "p"),
+                                   float(lam), float(L), int(n_iter), int(n_prox), BC[bc], lp))

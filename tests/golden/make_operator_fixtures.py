@@ -7,7 +7,8 @@ sHd 2048 patterns (column scramble seed 4, rows seed 5).
 
 Stored (float64 .npz, one file per case):
   forward_*:  columns `cols` of f = C A p0 for all 740 samples
-  adjoint_*:  slices z in `zs` of A^T C^T y with y = N(0,1) data (seed 5 / 6)
+  adjoint_*:  slices z in `zs` (the sensor plane z = 0, two interior slices, one
+              slice of the z-PML slab) of A^T C^T y with y = N(0,1) data (seed 5 / 6)
 Run: python tests/golden/make_operator_fixtures.py   (about 25 min on 8 cores)
 """
 
@@ -27,7 +28,7 @@ from synthetic import gaussian_data, vessel_phantom  # noqa: E402
 OUT = os.path.dirname(os.path.abspath(__file__))
 N, NT, P = 128, 740, 8
 COLS = np.arange(0, 2048, 64, dtype=np.int64)          # 32 data columns
-ZS = np.array([1, 60], dtype=np.int64)                 # two z slices of the adjoint
+ZS = np.array([0, 1, 60, 119], dtype=np.int64)         # z slices of the adjoint: sensor plane, interior, z-PML
 
 
 def main(which=("forward_points", "forward_hadamard", "adjoint_points", "adjoint_hadamard")):

@@ -1,9 +1,12 @@
 """Full-size (128^3, Nt = 740) GPU parity of A and A^T, in the configuration the
 benchmark times, on outputs sampled from the FP64 oracle.
 
-The oracle values were written by tests/golden/make_operator_fixtures.py
-(oracle only): 32 data columns of C A p0 for all 740 samples, and two z-slices
-of A^T C^T y. Tolerance: 1e-5 relative L2 over the sampled entries.
+The oracle values were written by tests/golden/make_operator_fixtures.py and
+tests/golden/make_solver_fixtures.py (oracle only): 32 data columns and the norm of
+C A p0 for all 740 samples; four z-slices of A^T C^T y (the sensor plane z = 0, two
+interior slices, one slice of the z-PML slab) and its norm; and a 1 x 2 TV+Br
+reconstruction (both sampling modes). Tolerances: 1e-5 relative L2 for A and
+A^T, 1e-4 for the reconstruction, over the sampled entries and for the norms.
 """
 
 import os
@@ -19,6 +22,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 N, NT, P = 128, 740, 8
 TOL_OP = 1e-5
+TOL_RECON = 1e-4
 
 
 def _fixture(case):
@@ -50,6 +54,7 @@ def test_forward_128(kind):
     full_norm_err = abs(np.linalg.norm(to_host(f)) - float(fx["norm"])) / float(fx["norm"])
     print(f"128^3 forward {kind}: rel L2 over sampled columns {err:.3e}; |f| rel diff {full_norm_err:.3e}")
     assert err < TOL_OP
+    assert full_norm_err < TOL_OP
 
 
 @pytest.mark.parametrize("kind", ["points", "hadamard"])
@@ -60,10 +65,49 @@ def test_adjoint_128(kind):
     y = gaussian_data((NT, 2048), int(fx["data_seed"]))
     p = empty(plan.vol_shape)
     Pb.pat_adjoint(plan, to_dev(y), p)
-    got = to_host(p)[fx["zs"]]
+    full = to_host(p)
+    got = full[fx["zs"]]
     err = rel_l2(got, fx["values"])
-    print(f"128^3 adjoint {kind} (white-noise data): rel L2 over sampled slices {err:.3e}")
-    assert err < TOL_OP
+    per_slice = {int(z): rel_l2(got[i], fx["values"][i]) for i, z in enumerate(fx["zs"])}
+    norm_err = abs(np.linalg.norm(full) - float(fx["norm"])) / float(fx["norm"])
+    print(f"128^3 adjoint {kind} (white-noise data): rel L2 over sampled slices {err:.3e}; per slice "
+          + ", ".join(f"z={z}: {e:.2e}" for z, e in per_slice.items()) + f"; |p| rel diff {norm_err:.3e}")
+    assert {0, N - P - 1} <= set(per_slice)          # the sensor plane and a z-PML slice are sampled
+    assert err < TOL_OP and norm_err < TOL_OP
+    # each slice on its own (the z-PML slice is small, so its relative error is looser)
+    assert all(e < 10 * TOL_OP for e in per_slice.values())
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard"])
+def test_reconstruction_128(kind):
+    """One Bregman step of 2 FISTA iterations (50 PDHG steps, Dirichlet TV, restart on) at 128^3.
+
+    Against the FP64 oracle run stored by tests/golden/make_solver_fixtures.py; the data are
+    this library's C A p0 plus the oracle's sigma times the same seeded noise. Flags must be
+    identical; energies, residuals, the Bregman residual, sampled z-slices (the sensor plane
+    included) and the norm of the reconstruction within 1e-4.
+    """
+    from paper_1605_00133_amd import pat as Pb
+    fx = _fixture(f"recon128_{kind}")
+    plan = _plan(kind)
+    p0 = vessel_phantom((N, N, N), P, 24, 1.0, 4.0, 1)
+    f = empty(plan.data_shape)
+    Pb.pat_forward(plan, to_dev(p0), f)
+    f += float(fx["sigma"]) * to_dev(gaussian_data((NT, 2048), 3))
+    p = empty(plan.vol_shape)
+    out = Pb.pat_reconstruct(plan, f, p, float(fx["lam"]), float(fx["L"]), 1, 2, 50, "dirichlet", restart=True)
+    full = to_host(p)
+    err = rel_l2(full[fx["zs"]], fx["values"])
+    norm_err = abs(np.linalg.norm(full) - float(fx["norm"])) / float(fx["norm"])
+    print(f"128^3 TV+Br 1x2 {kind}: rel L2 over z-slices {list(fx['zs'])} {err:.3e}; |p| rel diff {norm_err:.3e}; "
+          f"flags GPU {list(out['flags'])} oracle {list(fx['flags'])}")
+    print("energies GPU", out["energy"], "oracle", fx["energy"], "Bregman residual", out["bregman_residual"],
+          fx["bregman_residual"])
+    assert list(out["flags"]) == list(fx["flags"])
+    assert np.allclose(out["energy"], fx["energy"], rtol=TOL_RECON)
+    assert np.allclose(out["residual"], fx["residual"], rtol=TOL_RECON)
+    assert np.allclose(out["bregman_residual"], fx["bregman_residual"], rtol=TOL_RECON)
+    assert err < TOL_RECON and norm_err < TOL_RECON
 
 
 @pytest.mark.parametrize("kind", ["points"])

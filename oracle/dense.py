@@ -67,6 +67,46 @@ def dense_forward_matrix(g):
     return np.vstack(rows)
 
 
+def dense_time_reversal_matrix(g):
+    """Time reversal A^< as a dense N x (Nt*Ny*Nx) matrix (columns: the plane series y
+    flattened (n, iy, ix)), from the same explicit derivative matrices: zero fields, the
+    density components on the plane z = 0 replaced by y^(Nt-1-n) / (3 c0^2) at the start
+    and after every density update, the pressure field after the last step."""
+    N = g.nx * g.ny * g.nz
+    npix = g.nx * g.ny
+    M = g.nt * npix
+    dp, dm = dense_derivatives(g)
+    pml = pml_factors(g)
+    ones = (np.ones(g.nx), np.ones(g.ny), np.ones(g.nz))
+
+    def expand(vec, axis):
+        f = [ones[0][None, None, :], ones[1][None, :, None], ones[2][:, None, None]]
+        shp = [(1, 1, g.nx), (1, g.ny, 1), (g.nz, 1, 1)][axis]
+        f[axis] = vec.reshape(shp)
+        return (f[0] * f[1] * f[2]).ravel()
+
+    def inject(k):
+        E = np.zeros((npix, M))
+        E[np.arange(npix), k * npix + np.arange(npix)] = 1.0
+        return E
+
+    a = [expand(pml["a"][i], i) for i in range(3)]
+    b = [expand(pml["b"][i], i) for i in range(3)]
+    c2 = g.c0 ** 2
+    R = [np.zeros((N, M)) for _ in range(3)]
+    for i in range(3):
+        R[i][:npix] = inject(g.nt - 1) / (3.0 * c2)
+    U = [np.zeros((N, M)) for _ in range(3)]
+    P = c2 * (R[0] + R[1] + R[2])
+    for n in range(g.nt - 1):
+        U = [a[i][:, None] * (a[i][:, None] * U[i] - (g.dt / g.rho0) * (dp[i] @ P)) for i in range(3)]
+        R = [b[i][:, None] * (b[i][:, None] * R[i] - g.dt * g.rho0 * (dm[i] @ U[i])) for i in range(3)]
+        for i in range(3):
+            R[i][:npix] = inject(g.nt - 2 - n) / (3.0 * c2)
+        P = c2 * (R[0] + R[1] + R[2])
+    return P
+
+
 def dense_sampling_matrix(smp, n_pix):
     if smp.kind == "full":
         return np.eye(n_pix)

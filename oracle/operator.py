@@ -118,3 +118,29 @@ class WaveOperator:
         p = (rhoh[0] + rhoh[1] + rhoh[2]) / (3.0 * c2)
         p -= (g.dt / (2.0 * g.rho0)) * sum(self.dminus(v[xi], xi) for xi in range(3))
         return p
+
+    # -- time reversal A^< (eq. TRnum) ----------------------------------------------------------
+    def time_reversal(self, y):
+        """A^< applied to a plane series y [Nt][Ny][Nx]: the same recurrence run from zero
+        fields with the time-reversed series imposed on the detection plane as a Dirichlet
+        condition (Sec. 4.4): after the density update of every step (and at the start) each
+        density component on z = 0 is set to y^(Nt-1-n) / (3 c0^2), so that the pressure there
+        equals the datum; the output is the pressure field after the last step (whose plane
+        z = 0 is y^0)."""
+        g = self.g
+        y = np.asarray(y, dtype=np.float64)
+        nt = y.shape[0]
+        c2 = g.c0 * g.c0
+        rho = [np.zeros(g.shape) for _ in range(3)]
+        for xi in range(3):
+            rho[xi][0] = y[nt - 1] / (3.0 * c2)
+        u = [np.zeros(g.shape) for _ in range(3)]
+        p = c2 * (rho[0] + rho[1] + rho[2])
+        for n in range(nt - 1):
+            for xi in range(3):
+                u[xi] = self.a[xi] * (self.a[xi] * u[xi] - (g.dt / g.rho0) * self.dplus(p, xi))
+            for xi in range(3):
+                rho[xi] = self.b[xi] * (self.b[xi] * rho[xi] - g.dt * g.rho0 * self.dminus(u[xi], xi))
+                rho[xi][0] = y[nt - 2 - n] / (3.0 * c2)
+            p = c2 * (rho[0] + rho[1] + rho[2])
+        return p

@@ -35,21 +35,32 @@ from .tv import prox_tv_pos, tv_value
 
 
 class MeasuredOperator:
-    """x -> C A x and its transpose, on top of a WaveOperator and a Sampling."""
+    """x -> C W_s A x and its transpose, on top of a WaveOperator and a Sampling.
 
-    def __init__(self, wave, smp):
+    sens: optional sensor sensitivity W_s (eq. FwdSenVar), one weight per pixel of
+    the detection plane [Ny][Nx] scaling that pixel's pressure time course before
+    the sub-sampling; None is the ideal sensor (W_s = I)."""
+
+    def __init__(self, wave, smp, sens=None):
         self.wave = wave
         self.smp = smp
         g = wave.g
         self.in_shape = g.shape
         self.out_shape = (g.nt, smp.mc)
+        self.sens = None if sens is None else np.asarray(sens, dtype=np.float64).reshape(g.ny, g.nx)
 
     def forward(self, x):
-        return apply_c(self.wave.forward_planes(x), self.smp)
+        s = self.wave.forward_planes(x)
+        if self.sens is not None:
+            s = s * self.sens[None]
+        return apply_c(s, self.smp)
 
     def adjoint(self, r):
         g = self.wave.g
-        return self.wave.adjoint_planes(apply_ct(r, self.smp, g.ny, g.nx))
+        s = apply_ct(r, self.smp, g.ny, g.nx)
+        if self.sens is not None:
+            s = s * self.sens[None]
+        return self.wave.adjoint_planes(s)
 
 
 @dataclass

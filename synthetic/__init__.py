@@ -9,8 +9,9 @@ experimental data are not available; random tubular vessel phantoms of the
 same grid sizes stand in for them.
 """
 
-from .phantoms import vessel_phantom, moving_vessel_frames, gaussian_volume, gaussian_data, gaussian_blob
+from .phantoms import (vessel_phantom, moving_vessel_frames, gaussian_volume, gaussian_data, gaussian_blob,
+                       lognormal_weights)
 from .configs import CONFIGS, make_grid_params
 
-__all__ = ["vessel_phantom", "moving_vessel_frames", "gaussian_volume", "gaussian_data", "gaussian_blob",
+__all__ = ["vessel_phantom", "moving_vessel_frames", "gaussian_volume", "gaussian_data", "gaussian_blob", "lognormal_weights",
            "CONFIGS", "make_grid_params"]

@@ -141,3 +141,9 @@ def gaussian_blob(shape, centre, sigma):
     zz, yy, xx = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
     r2 = (zz - centre[0]) ** 2 + (yy - centre[1]) ** 2 + (xx - centre[2]) ** 2
     return np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def lognormal_weights(shape, sigma, seed):
+    """w = exp(sigma X), X ~ N(0, 1) seeded (the paper's model of a spatially varying
+    sensor sensitivity, sigma = 0.2, and of the noise level per sensor, sigma = 0.1)."""
+    return np.exp(sigma * gaussian_data(shape, seed))

@@ -163,3 +163,43 @@ def test_pml_suppresses_wraparound():
     # the big domain has no wrap-around within nt steps (its images are > 50 cells away)
     print("PML reflection (rel L2 on the sensor core):", rel)
     assert rel < 1e-2         # better than -40 dB
+
+
+@pytest.mark.parametrize("kind", ["points", "hadamard"])
+def test_sensor_sensitivity_weights(kind):
+    """eq. FwdSenVar: C W_s A. W_s = I changes nothing; each sampled pixel's series is its
+    unweighted series times that pixel's weight (random points); the weighted pair stays
+    an exact transpose (adjoint identity, 1e-12)."""
+    from oracle.solvers import MeasuredOperator
+    from synthetic import gaussian_data, lognormal_weights
+    g = Grid(16, 16, 16, dx=1e-4, c0=1500.0, dt=2e-8, nt=30, pml_size=4)
+    wave = WaveOperator(g)
+    smp = Sampling.points(256, 64, 2) if kind == "points" else Sampling.hadamard(256, 32, 4)
+    w = lognormal_weights((16, 16), 0.2, 9)
+    x = gaussian_data(g.shape, 1)
+    plain, ones, wtd = MeasuredOperator(wave, smp), MeasuredOperator(wave, smp, np.ones((16, 16))), \
+        MeasuredOperator(wave, smp, w)
+    assert np.array_equal(ones.forward(x), plain.forward(x))
+    if kind == "points":
+        assert np.allclose(wtd.forward(x), plain.forward(x) * w.ravel()[smp.idx][None, :], rtol=1e-13, atol=1e-15)
+    y = gaussian_data((30, smp.mc), 2)
+    lhs = float(np.vdot(wtd.forward(x), y))
+    rhs = float(np.vdot(x, wtd.adjoint(y)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("pml", [0, 2])
+def test_time_reversal_dense_bruteforce_8cubed(pml):
+    """Time reversal (eq. TRnum) against its dense matrix built from explicit DFT sums
+    (no FFT library), 1e-12; the output's sensor plane is the first datum; linear."""
+    from oracle.dense import dense_time_reversal_matrix
+    from synthetic import gaussian_data
+    g = Grid(8, 8, 8, dx=1e-4, c0=1500.0, dt=2e-8, nt=12, pml_size=pml)
+    op = WaveOperator(g)
+    y = gaussian_data((12, 8, 8), 4)
+    got = op.time_reversal(y)
+    ref = (dense_time_reversal_matrix(g) @ y.ravel()).reshape(g.shape)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.allclose(got[0], y[0], rtol=1e-14, atol=1e-14)
+    assert np.allclose(op.time_reversal(2.5 * y), 2.5 * got, rtol=1e-13, atol=1e-13)
+    assert not np.allclose(got[1:], 0.0)

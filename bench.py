@@ -20,10 +20,11 @@ Besides the value (all outside the timed region): operator-only pairs/s; the
 per-kernel HIP-event timing of one pair (roofline of the dominant kernel); the
 error of this run's A and A^T against stored FP64 oracle samples; the other
 sampling mode's rates; 2 and 4 independent problems at once (4 x 0.5 GB is
-above the 256 MB last-level cache); the time-to-target curve of plain TV+Br
-(5 x 50, PSNR and wall time per iteration) and, when trained weights are
-present, the learned reconstruction against it; the FP64 oracle timed on the
-host (all cores and one core).
+above the 256 MB last-level cache); with patterned interrogation (the learned
+update's workload) the time-to-target curve of plain TV+Br (5 x 50, PSNR and
+wall time per iteration) and, when trained weights are present, the learned
+reconstruction against it; the FP64 oracle timed on the host (all cores and
+one core).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -110,6 +111,15 @@ def fp64_error(P, torch, prob):
         out["adjoint_sampled_slices"] = rel_l2(ph[fx["zs"]], fx["values"])
         out["adjoint_norm"] = abs(np.linalg.norm(ph) - float(fx["norm"])) / float(fx["norm"])
     return out or None
+
+
+def ensure_lambda(prob):
+    """A grid other than the frozen workload's has no calibrated lambda: the frozen fraction of
+    sigma sqrt(Nt M_c) of the random-point calibration stands in."""
+    if prob["lam_br"] is None:
+        prob["lam_tv"] = 6.3e-4 * prob["sigma"] * np.sqrt(prob["plan"].data_shape[0] * prob["mc"])
+        prob["lam_br"] = 10.0 * prob["lam_tv"]
+    return prob
 
 
 def fista_rate(P, torch, prob, steps, warmup, n_prox):
@@ -230,10 +240,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, nt = args.n, args.nt
-    prob = paper_problem(args.sampling, n, nt)
-    if prob["lam_br"] is None:   # a grid other than the frozen workload's: the rule of thumb
-        prob["lam_tv"] = 6.3e-4 * prob["sigma"] * np.sqrt(prob["plan"].data_shape[0] * prob["mc"])
-        prob["lam_br"] = 10.0 * prob["lam_tv"]
+    prob = ensure_lambda(paper_problem(args.sampling, n, nt))
     plan, mc = prob["plan"], prob["mc"]
     log(f"plan {n}^3 nt={nt} {args.sampling} mc={mc}: workspace {plan.workspace.numel() / 2**20:.0f} MiB; "
         f"L = {prob['L']:.4e}, sigma = {prob['sigma']:.3e}, lambda_TV+ = {prob['lam_tv']:.4e}, "
@@ -284,17 +291,13 @@ def main():
     other = None
     if args.other_sampling:
         kind = "hadamard" if args.sampling == "points" else "points"
-        prob2 = paper_problem(kind, n, nt)
-        if prob2["lam_br"] is None:
-            prob2["lam_tv"] = 6.3e-4 * prob2["sigma"] * np.sqrt(prob2["plan"].data_shape[0] * prob2["mc"])
-            prob2["lam_br"] = 10.0 * prob2["lam_tv"]
+        prob2 = ensure_lambda(paper_problem(kind, n, nt))
         pr2, el2, _ = fista_rate(P, torch, prob2, max(2, args.steps // 2), 1, args.n_prox)
         other = {"sampling": kind, "fista_pairs_per_s": round(pr2 / el2, 4),
                  "operator_pairs_per_s": round(operator_rate(P, torch, prob2), 4),
                  "fp64_error": fp64_error(P, torch, prob2), "lam_tv": prob2["lam_tv"]}
         log(f"{kind}: {other['fista_pairs_per_s']:.2f} pairs/s in FISTA, {other['operator_pairs_per_s']:.2f} "
             f"operator pairs/s")
-        prob2["plan"].close()
 
     # ---- independent problems at once (above the last-level cache at 4) -----------------------
     concurrent = []
@@ -306,21 +309,32 @@ def main():
         log(f"concurrent: {K} problems, {agg:.2f} operator pairs/s aggregate ({agg / op_pairs_s:.2f}x one), "
             f"workspaces {ws / 2**20:.0f} MiB")
 
-    # ---- time to target PSNR: plain TV+Br, and the learned iteration if trained -----------------
+    # ---- time to target PSNR (patterned interrogation, the learned update's workload): plain TV+Br,
+    # and the learned iteration if trained weights are present ----------------------------------
     ttt = None
     if not args.no_time_to_target:
-        c = tv_bregman_curve(prob, n_prox=args.n_prox)
-        ttt = {"tv_bregman": {k: v for k, v in c.items() if k not in ("p", "psnr", "t_ms")}}
+        if args.sampling == "hadamard":
+            prob_t = prob
+        elif other is not None:
+            prob_t = prob2
+        else:
+            prob_t = ensure_lambda(paper_problem("hadamard", n, nt))
+        c = tv_bregman_curve(prob_t, n_prox=args.n_prox)
+        ttt = {"sampling": prob_t["sampling"], "lambda_br": prob_t["lam_br"],
+               "tv_bregman": {k: v for k, v in c.items() if k not in ("p", "psnr", "t_ms")}}
         ttt["tv_bregman"]["psnr_every_10"] = [round(float(x), 3) for x in c["psnr"][9::10]]
         ttt["tv_bregman"]["t_ms_every_10"] = [round(float(x), 1) for x in c["t_ms"][9::10]]
         log(f"TV+Br 5x50: final {c['final_psnr_db']:.2f} dB after {c['total_ms'] / 1e3:.2f} s; within 0.5 dB "
             f"({c['target_psnr_db']:.2f} dB) at {c['t_target_ms']:.0f} ms (iteration {c['target_iteration']})")
         try:
             from paper_1605_00133_amd.learned_unet import bench_learned
-            ttt["learned"] = bench_learned(prob, c, log=log)
+            ttt["learned"] = bench_learned(prob_t, c, log=log)
         except (ImportError, FileNotFoundError) as e:
             ttt["learned"] = None
             log(f"learned: not run ({e})")
+
+    if other is not None:
+        prob2["plan"].close()
 
     cpu = None
     if not args.no_cpu_baseline:

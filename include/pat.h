@@ -100,6 +100,26 @@ pat_status pat_plan_create(const pat_grid* grid, const pat_sampling* smp, void* 
 pat_status pat_plan_destroy(pat_plan* plan);
 pat_status pat_plan_set_stream(pat_plan* plan, void* stream);
 
+/* Spatially varying sensor sensitivity W_s (eq. FwdSenVar, Sec. 5.3): with a
+ * weight per pixel of the detection plane, pat_forward computes C W_s A p0 (each
+ * pixel's pressure time course scaled by its weight before sub-sampling) and
+ * pat_adjoint A^T W_s C^T f, so the pair stay exact transposes. w: HOST array of
+ * nx*ny finite floats [iy][ix], copied into a device buffer the plan owns (one
+ * allocation on the first call); NULL restores the ideal sensor. Used to
+ * generate data with a model other than the one reconstructed with. */
+pat_status pat_plan_set_sensitivity(pat_plan* plan, const float* w);
+
+/* A heterogeneous medium for data generation (the sound-speed perturbation of
+ * the no-inverse-crime data, Sec. 5.3): c is a HOST array of nz*ny*nx speeds
+ * [z][y][x], each positive and at most the grid's c0, which becomes the reference
+ * speed of the k-space correction (and of the CFL number). pat_forward then
+ * computes the pressure as c(x)^2 times the summed densities, with initial
+ * densities p0 / (3 c(x)^2), on the slab scheme whatever the plan's scheme.
+ * pat_adjoint, pat_time_reversal and pat_reconstruct need the homogeneous medium
+ * and return PAT_ERR_UNSUPPORTED while a field is set; NULL clears it. The field
+ * is copied into a device buffer the plan owns (allocated on the first call). */
+pat_status pat_plan_set_sound_speed(pat_plan* plan, const float* c);
+
 /* Arithmetic of the propagator's FFT butterflies: 64 (default) keeps FP64
  * values in registers and LDS inside each transform pass and rounds to FP32
  * once per pass; 32 computes in FP32 throughout (faster, about 5x larger
@@ -130,6 +150,17 @@ pat_status pat_forward(pat_plan* plan, const float* p0, float* f);
 /* p = A^T C^T f, the exact transpose of pat_forward's arithmetic (eq. BP).
  * f: device [nt][mc]; p: device [nz][ny][nx]; no overlap. */
 pat_status pat_adjoint(pat_plan* plan, const float* f, float* p);
+
+/* p = A^< C^T f, time reversal (eq. TRnum, Sec. 4.4): the propagator run from
+ * zero fields with the time-reversed series C^T f imposed on the detection plane
+ * as a Dirichlet condition (at the start and after every density update, each
+ * density component on z = 0 is set to the datum / (3 c0^2)); p is the pressure
+ * field after the last step (its plane z = 0 is the datum at t = 0). A linear
+ * two-step baseline, not an adjoint. Runs the slab scheme (real-space fields)
+ * with the plan's FFT precision whatever the plan's scheme, ignores the sensor
+ * sensitivity, and cannot be captured into a graph (PAT_ERR_UNSUPPORTED).
+ * f: device [nt][mc]; p: device [nz][ny][nx]; no overlap. */
+pat_status pat_time_reversal(pat_plan* plan, const float* f, float* p);
 
 /* C alone on a plane series s: device [nt][ny][nx] -> f: device [nt][mc]. */
 pat_status pat_sample(pat_plan* plan, const float* s, float* f);

@@ -37,8 +37,10 @@ def dense_derivatives(g):
     return dp, dm
 
 
-def dense_forward_matrix(g):
-    """A as a dense matrix: rows (n, iy, ix), columns flattened p0."""
+def dense_forward_matrix(g, c=None):
+    """A as a dense matrix: rows (n, iy, ix), columns flattened p0; c: optional sound-speed
+    field (pressure c(x)^2 sum rho, initial densities p0 / (3 c(x)^2), k-space correction
+    with the grid's c0)."""
     N = g.nx * g.ny * g.nz
     npix = g.nx * g.ny
     dp, dm = dense_derivatives(g)
@@ -53,16 +55,16 @@ def dense_forward_matrix(g):
 
     a = [expand(pml["a"][i], i) for i in range(3)]
     b = [expand(pml["b"][i], i) for i in range(3)]
-    c2 = g.c0 ** 2
+    c2 = np.full(N, g.c0 ** 2) if c is None else np.asarray(c, dtype=np.float64).ravel() ** 2
     I = np.eye(N)
-    R = [I / (3.0 * c2) for _ in range(3)]
+    R = [I / (3.0 * c2[:, None]) for _ in range(3)]
     U = [(g.dt / (2.0 * g.rho0)) * dp[i] for i in range(3)]
     P = I
     rows = [P[:npix]]
     for _ in range(g.nt - 1):
         U = [a[i][:, None] * (a[i][:, None] * U[i] - (g.dt / g.rho0) * (dp[i] @ P)) for i in range(3)]
         R = [b[i][:, None] * (b[i][:, None] * R[i] - g.dt * g.rho0 * (dm[i] @ U[i])) for i in range(3)]
-        P = c2 * (R[0] + R[1] + R[2])
+        P = c2[:, None] * (R[0] + R[1] + R[2])
         rows.append(P[:npix])
     return np.vstack(rows)
 

@@ -43,9 +43,14 @@ def _workers():
 class WaveOperator:
     """A: R^{Nz x Ny x Nx} -> R^{Nt x Ny x Nx} (detection-plane time series)."""
 
-    def __init__(self, grid, workers=None):
+    def __init__(self, grid, workers=None, c=None):
+        """c: optional sound-speed field [Nz][Ny][Nx] (the no-inverse-crime data model of
+        Sec. 5.3); the pressure is then p = c(x)^2 sum_xi rho_xi and the initial densities
+        p0 / (3 c(x)^2), while the k-space correction keeps the grid's c0 as the reference
+        speed. None: homogeneous c0 everywhere."""
         self.g = grid
         self.workers = workers or _workers()
+        self.c2 = None if c is None else np.asarray(c, dtype=np.float64).reshape(grid.shape) ** 2
         g = grid
         kap = kappa_grid(g)
         ks = (wavenumbers(g.nx, g.dx)[None, None, :],
@@ -75,7 +80,7 @@ class WaveOperator:
         g = self.g
         nt = g.nt if nsteps is None else nsteps
         p0 = np.asarray(p0, dtype=np.float64)
-        c2 = g.c0 * g.c0
+        c2 = g.c0 * g.c0 if self.c2 is None else self.c2
         rho = [p0 / (3.0 * c2) for _ in range(3)]
         u = [(g.dt / (2.0 * g.rho0)) * self.dplus(p0, xi) for xi in range(3)]
         s = np.empty((nt, g.ny, g.nx))
@@ -92,7 +97,9 @@ class WaveOperator:
 
     # -- A^T -------------------------------------------------------------------
     def adjoint_planes(self, y):
-        """Exact transpose of forward_planes: [Nt][Ny][Nx] -> [Nz][Ny][Nx]."""
+        """Exact transpose of forward_planes: [Nt][Ny][Nx] -> [Nz][Ny][Nx] (homogeneous c0)."""
+        if self.c2 is not None:
+            raise NotImplementedError("the adjoint is built for the homogeneous sound speed only")
         g = self.g
         y = np.asarray(y, dtype=np.float64)
         nt = y.shape[0]
@@ -128,6 +135,8 @@ class WaveOperator:
         equals the datum; the output is the pressure field after the last step (whose plane
         z = 0 is y^0)."""
         g = self.g
+        if self.c2 is not None:
+            raise NotImplementedError("time reversal is built for the homogeneous sound speed only")
         y = np.asarray(y, dtype=np.float64)
         nt = y.shape[0]
         c2 = g.c0 * g.c0

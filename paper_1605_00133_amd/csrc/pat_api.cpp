@@ -207,6 +207,8 @@ struct pat_plan {
   LineTables ltabs;
   LineScalars lsc;
   LineBuffers lb;
+  float* sens;              // per-pixel sensor sensitivity W_s (owned device copy) or null
+  float* c2f;               // c(x)^2 of a heterogeneous medium (owned device copy) or null
   KernelTimer timer;        // active when timer.ev != nullptr
   std::vector<hipEvent_t> timer_events;
   std::vector<int> timer_ids;
@@ -386,7 +388,9 @@ long vol_n(const pat_plan* P) { return (long)n_voxels(P->g); }
 long data_n(const pat_plan* P) { return (long)P->g.nt * P->mc; }
 
 // ---- operator pieces used by the entry points and the solver ----------------
-bool use_line(const pat_plan* P) { return P->scheme == PAT_SCHEME_LINE && P->limpl && P->fftp == FFT_FP64; }
+bool use_line(const pat_plan* P) {
+  return P->scheme == PAT_SCHEME_LINE && P->limpl && P->fftp == FFT_FP64 && !P->c2f;
+}
 
 // The slab scheme tags its hand-off flags with an epoch the host advances per
 // launch; a graph would replay stale epochs, so that scheme refuses capture.
@@ -412,6 +416,7 @@ pat_status op_forward(pat_plan* P, const float* p0, float* f) {
                                           P->handoff));
     PAT_TRY_HIP(launch_sum2(P->planes2, nplane, planes, nplane, P->stream));
   }
+  if (P->sens) PAT_TRY_HIP(launch_scale_pixels(planes, P->sens, planes, P->g.nt, P->npix, P->stream));
   if (P->kind == PAT_SAMPLE_POINTS)
     PAT_TRY_HIP(launch_rsp_gather(planes, P->idx, f, P->npix, P->mc, P->g.nt, P->stream));
   else if (P->kind == PAT_SAMPLE_HADAMARD)
@@ -420,6 +425,8 @@ pat_status op_forward(pat_plan* P, const float* p0, float* f) {
 }
 
 pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
+  if (P->c2f)
+    return set_error(PAT_ERR_UNSUPPORTED, "the adjoint is built for a homogeneous medium (clear the sound-speed field)");
   PAT_TRY(check_capture(P));
   const float* planes = f;
   if (P->kind == PAT_SAMPLE_POINTS) {
@@ -428,6 +435,11 @@ pat_status op_adjoint(pat_plan* P, const float* f, float* p) {
   } else if (P->kind == PAT_SAMPLE_HADAMARD) {
     PAT_TRY_HIP(launch_shd_adjoint(f, P->invperm, P->idx, P->planes, P->npix, P->mc, P->g.nt, P->stream));
     planes = P->planes;
+  }
+  if (P->sens) {   // W_s is diagonal: its transpose is itself (FULL: f is read-only, scale into planes2)
+    float* dst = P->kind == PAT_SAMPLE_FULL ? P->planes2 : P->planes;
+    PAT_TRY_HIP(launch_scale_pixels(planes, P->sens, dst, P->g.nt, P->npix, P->stream));
+    planes = dst;
   }
   KernelTimer* kt = P->timer.ev ? &P->timer : nullptr;
   if (use_line(P))
@@ -584,6 +596,11 @@ pat_status pat_plan_destroy(pat_plan* plan) {
   if (!plan) return PAT_OK;
   pat_status st = PAT_OK;
   for (hipEvent_t e : plan->timer_events) (void)hipEventDestroy(e);
+  if (plan->sens || plan->c2f) {
+    DeviceGuard dg(plan->device);
+    if (plan->sens) (void)hipFree(plan->sens);
+    if (plan->c2f) (void)hipFree(plan->c2f);
+  }
   if (plan->tables) {
     DeviceGuard dg(plan->device);
     hipError_t e = hipFree(plan->tables);
@@ -596,6 +613,46 @@ pat_status pat_plan_destroy(pat_plan* plan) {
 pat_status pat_plan_set_stream(pat_plan* plan, void* stream) {
   PAT_TRY(check_plan(plan));
   plan->stream = static_cast<hipStream_t>(stream);
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_sensitivity(pat_plan* plan, const float* w) {
+  PAT_TRY(check_plan(plan));
+  DeviceGuard dg(plan->device);
+  if (!w) {
+    if (plan->sens) PAT_TRY_HIP(hipFree(plan->sens));
+    plan->sens = nullptr;
+    return PAT_OK;
+  }
+  for (int i = 0; i < plan->npix; ++i)
+    if (!std::isfinite(w[i])) return set_error(PAT_ERR_INVALID, "pat_plan_set_sensitivity: w[%d] is not finite", i);
+  if (!plan->sens) PAT_TRY_HIP(hipMalloc(&plan->sens, (size_t)plan->npix * sizeof(float)));
+  PAT_TRY_HIP(hipMemcpy(plan->sens, w, (size_t)plan->npix * sizeof(float), hipMemcpyHostToDevice));
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_sound_speed(pat_plan* plan, const float* c) {
+  PAT_TRY(check_plan(plan));
+  DeviceGuard dg(plan->device);
+  if (!c) {
+    if (plan->c2f) PAT_TRY_HIP(hipFree(plan->c2f));
+    plan->c2f = nullptr;
+    plan->wb.c2f = nullptr;
+    return PAT_OK;
+  }
+  const long nv = vol_n(plan);
+  std::vector<float> c2(nv);
+  for (long i = 0; i < nv; ++i) {
+    if (!(c[i] > 0) || !std::isfinite(c[i]))
+      return set_error(PAT_ERR_INVALID, "pat_plan_set_sound_speed: c[%ld] must be positive and finite", i);
+    if (c[i] > plan->g.c0 * (1.0 + 1e-6))
+      return set_error(PAT_ERR_INVALID, "pat_plan_set_sound_speed: c[%ld] = %g exceeds the reference c0 = %g", i,
+                       (double)c[i], plan->g.c0);
+    c2[i] = (float)((double)c[i] * (double)c[i]);
+  }
+  if (!plan->c2f) PAT_TRY_HIP(hipMalloc(&plan->c2f, (size_t)nv * sizeof(float)));
+  PAT_TRY_HIP(hipMemcpy(plan->c2f, c2.data(), (size_t)nv * sizeof(float), hipMemcpyHostToDevice));
+  plan->wb.c2f = plan->c2f;
   return PAT_OK;
 }
 
@@ -632,6 +689,39 @@ pat_status pat_adjoint(pat_plan* plan, const float* f, float* p) {
     return set_error(PAT_ERR_INVALID, "pat_adjoint: f and p overlap");
   DeviceGuard dg(plan->device);
   return op_adjoint(plan, f, p);
+}
+
+pat_status pat_time_reversal(pat_plan* plan, const float* f, float* p) {
+  PAT_TRY(check_plan(plan));
+  if (!p || !f) return set_error(PAT_ERR_INVALID, "pat_time_reversal: null pointer");
+  if (overlaps(p, vol_bytes(plan), f, data_bytes(plan)))
+    return set_error(PAT_ERR_INVALID, "pat_time_reversal: f and p overlap");
+  DeviceGuard dg(plan->device);
+  pat_plan* P = plan;
+  if (P->c2f)
+    return set_error(PAT_ERR_UNSUPPORTED, "time reversal is built for a homogeneous medium (clear the sound-speed field)");
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PAT_TRY_HIP(hipStreamIsCapturing(P->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return set_error(PAT_ERR_UNSUPPORTED, "pat_time_reversal runs the slab scheme, which cannot be captured");
+  }
+  const float* planes = f;   // C^T f (the pseudo-inverse of C, Sec. 4.4)
+  if (P->kind == PAT_SAMPLE_POINTS) {
+    PAT_TRY_HIP(launch_rsp_scatter(f, P->inv, P->planes, P->npix, P->mc, P->g.nt, P->stream));
+    planes = P->planes;
+  } else if (P->kind == PAT_SAMPLE_HADAMARD) {
+    PAT_TRY_HIP(launch_shd_adjoint(f, P->invperm, P->idx, P->planes, P->npix, P->mc, P->g.nt, P->stream));
+    planes = P->planes;
+  }
+  float *vol = P->img[IMG_VCOPY], *pa = P->img[IMG_V], *pb = P->img[IMG_QBAR];
+  PAT_TRY_HIP(P->impl->time_reversal[P->fftp](P->tabs, P->sc, P->wb, planes, vol, pa, pb, P->planes2, P->g.nt,
+                                                P->stream, P->handoff));
+  if (P->g.nt == 1)
+    PAT_TRY_HIP(launch_scale(vol, p, 1.f, vol_n(P), P->stream));
+  else
+    PAT_TRY_HIP(launch_axpy(pa, pb, p, 1.f, vol_n(P), P->stream));
+  return PAT_OK;
 }
 
 pat_status pat_sample(pat_plan* plan, const float* s, float* f) {

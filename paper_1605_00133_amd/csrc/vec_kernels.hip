@@ -274,6 +274,13 @@ __global__ __launch_bounds__(kThreadsVec) void k_sum2(const float* __restrict__ 
   if (i < n) out[i] = a[i] + a[i + stride];
 }
 
+// out[t][i] = w[i] * a[t][i] for the plane series [nt][npix] (sensor sensitivity, eq. FwdSenVar)
+__global__ __launch_bounds__(kThreadsVec) void k_scale_pixels(const float* __restrict__ a, const float* __restrict__ w,
+                                                             float* __restrict__ out, long n, int npix) {
+  const long i = (long)blockIdx.x * kThreadsVec + threadIdx.x;
+  if (i < n) out[i] = w[i % npix] * a[i];
+}
+
 __global__ __launch_bounds__(kThreadsVec) void k_fill(float* __restrict__ out, float v, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = v;
@@ -364,6 +371,13 @@ hipError_t launch_scale(const float* a, float* out, float s, long n, hipStream_t
 hipError_t launch_sum2(const float* a, long stride, float* out, long n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   k_sum2<<<nblocks(n), kThreadsVec, 0, st>>>(a, stride, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_pixels(const float* a, const float* w, float* out, int nt, int npix, hipStream_t st) {
+  const long n = (long)nt * npix;
+  if (n == 0) return hipSuccess;
+  k_scale_pixels<<<nblocks(n), kThreadsVec, 0, st>>>(a, w, out, n, npix);
   return hipGetLastError();
 }
 

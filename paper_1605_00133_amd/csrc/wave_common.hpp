@@ -55,6 +55,7 @@ struct WaveBuffers {
   float* u[3];           // velocity components (staggered), [nz][ny][nx]
   float* rho[3];         // split density components
   float2* spec[4];       // slab spectra [nz][nx/2+1][ny]
+  const float* c2f;      // forward only: c(x)^2 [nz][ny][nx] of a heterogeneous medium, or null (c0^2)
 };
 
 // Kernels of one time step, for per-kernel timing.
@@ -131,10 +132,16 @@ using WaveLaunchAdj = hipError_t (*)(const WaveTables&, const WaveScalars&, cons
 // LDS with FP32 storage in HBM.
 enum FftPrecision { FFT_FP32 = 0, FFT_FP64 = 1 };
 
+// time reversal: planes [nt][ny][nx] -> p = p_a + p_b (nt > 1) or vol (nt = 1); see wave_kernels.hip
+using WaveLaunchTR = hipError_t (*)(const WaveTables&, const WaveScalars&, const WaveBuffers&, const float* planes,
+                                    float* vol, float* p_a, float* p_b, float* tplanes, int nt, hipStream_t,
+                                    HandOff&);
+
 struct WaveImpl {
   int nx, ny, nz;
   WaveLaunchFwd forward[2];   // indexed by FftPrecision
   WaveLaunchAdj adjoint[2];
+  WaveLaunchTR time_reversal[2];
 };
 
 // Returns nullptr when the size is not built.

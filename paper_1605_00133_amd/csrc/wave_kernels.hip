@@ -842,7 +842,11 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_init(const float* __restri
     if (it.ok) {
 #pragma unroll
       for (int m = 0; m < D::RX0; ++m) {
-        const float2 r = make_float2(v[i][m].x * sc.inv_3c2, v[i][m].y * sc.inv_3c2);
+        float2 r = make_float2(v[i][m].x * sc.inv_3c2, v[i][m].y * sc.inv_3c2);
+        if (B.c2f) {   // heterogeneous medium: rho_xi = p0 / (3 c(x)^2)
+          const float2 cc = reinterpret_cast<const float2*>(B.c2f)[off + it.pair(m)];
+          r = make_float2(v[i][m].x / (3.0f * cc.x), v[i][m].y / (3.0f * cc.y));
+        }
 #pragma unroll
         for (int xi = 0; xi < 3; ++xi) reinterpret_cast<float2*>(B.rho[xi])[off + it.pair(m)] = r;
         if (z == 0) {
@@ -1118,11 +1122,16 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_u(const float2* __restrict
 // contributions go to plane_a / plane_b (summed after the run). The sums are
 // formed from the new components as stored (each thread re-reads its own
 // values), which keeps the transforms free of a live accumulator.
-template <int NX, int NY, int NZ, typename V>
+// TR: time reversal (eq. TRnum): on the slab z = 0 the density components are set to
+// dir / (3 c0^2) (the datum imposed on the detection plane, a Dirichlet condition)
+// instead of being updated, and, if p_a / p_b are given, each half stores its part of
+// the real pressure (half 0: c0^2 (rho_x + rho_y), half 1: c0^2 rho_z).
+template <int NX, int NY, int NZ, typename V, bool TR = false>
 __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* H0, const float2* H1, const float2* H2,
                                                           WaveBuffers B, float2* Pa, float2* Pb,
                                                           float* __restrict__ plane_a, float* __restrict__ plane_b,
-                                                          WaveTables t, WaveScalars sc) {
+                                                          WaveTables t, WaveScalars sc, const float* __restrict__ dir,
+                                                          float* __restrict__ p_a, float* __restrict__ p_b) {
   using D = Dims<NX, NY, NZ>;
   __shared__ SlabLds<NX, NY, NZ, V> L;
   const int z = blockIdx.x >> 1, half = blockIdx.x & 1, tid = threadIdx.x;
@@ -1153,8 +1162,14 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* H0, cons
       if (xi == 0) { b0 = L.px[2 * n]; b1 = L.px[2 * n + 1]; }
       else if (xi == 1) { b0 = b1 = L.py[it.y]; }
       else { b0 = b1 = bzz; }
-      r[it.pair(m)] = make_float2(b0 * (b0 * ro[i][m].x - sc.dt_rho0 * h.x),
-                                  b1 * (b1 * ro[i][m].y - sc.dt_rho0 * h.y));
+      float2 rn = make_float2(b0 * (b0 * ro[i][m].x - sc.dt_rho0 * h.x), b1 * (b1 * ro[i][m].y - sc.dt_rho0 * h.y));
+      if constexpr (TR) {
+        if (z == 0) {
+          const float2 d = reinterpret_cast<const float2*>(dir)[it.pair(m)];
+          rn = make_float2(d.x * sc.inv_3c2, d.y * sc.inv_3c2);
+        }
+      }
+      r[it.pair(m)] = rn;
     });
   }
   float2 p[D::IX0][D::RX0], r1[D::IX0][D::RX0];
@@ -1169,8 +1184,17 @@ __global__ __launch_bounds__(kThreadsSlab) void k_fwd_rho(const float2* H0, cons
       for (int m = 0; m < D::RX0; ++m) {
         float2 v = p[i][m];
         if (nxi == 2) v = make_float2(v.x + r1[i][m].x, v.y + r1[i][m].y);
-        p[i][m] = make_float2(v.x * sc.c2, v.y * sc.c2);
+        if (B.c2f) {   // heterogeneous medium: p = c(x)^2 sum rho
+          const float2 cc = reinterpret_cast<const float2*>(B.c2f)[rz + it.pair(m)];
+          p[i][m] = make_float2(v.x * cc.x, v.y * cc.y);
+        } else {
+          p[i][m] = make_float2(v.x * sc.c2, v.y * sc.c2);
+        }
         if (z == 0) reinterpret_cast<float2*>(plane)[it.pair(m)] = p[i][m];
+        if constexpr (TR) {
+          float* po = half == 0 ? p_a : p_b;
+          if (po) reinterpret_cast<float2*>(po)[rz + it.pair(m)] = p[i][m];
+        }
       }
     }
   }
@@ -1553,7 +1577,8 @@ hipError_t wave_forward(const WaveTables& t, const WaveScalars& sc, const WaveBu
     timed(kt, K_FWD_RHO, st, [&] {
       k_fwd_rho<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0], B.spec[1],
                                                        planes + (size_t)(n + 1) * npix,
-                                                       planes + (size_t)(nt + n + 1) * npix, t, sc);
+                                                       planes + (size_t)(nt + n + 1) * npix, t, sc, nullptr, nullptr,
+                                                       nullptr);
     });
   }
   return hipGetLastError();
@@ -1593,9 +1618,45 @@ hipError_t wave_adjoint(const WaveTables& t, const WaveScalars& sc, const WaveBu
   return hipGetLastError();
 }
 
+// Time reversal (eq. TRnum): the forward recurrence from zero fields with the reversed
+// plane series imposed on z = 0 (k_fwd_rho<TR>). planes: [nt][ny][nx] (y^0 .. y^(nt-1));
+// vol: a scratch volume; p_a, p_b: the two halves of the final pressure (p = p_a + p_b;
+// for nt = 1 the pressure is vol itself); tplanes: 2 scratch planes.
+template <int NX, int NY, int NZ, typename V>
+hipError_t wave_time_reversal(const WaveTables& t, const WaveScalars& sc, const WaveBuffers& B, const float* planes,
+                              float* vol, float* p_a, float* p_b, float* tplanes, int nt, hipStream_t st,
+                              HandOff& ho) {
+  using D = Dims<NX, NY, NZ>;
+  constexpr int NT = kThreadsSlab;
+  const size_t npix = (size_t)NX * NY, nvox = npix * NZ;
+  hipError_t e = hipSuccess;
+  for (int xi = 0; xi < 3 && e == hipSuccess; ++xi) e = hipMemsetAsync(B.u[xi], 0, nvox * sizeof(float), st);
+  if (e == hipSuccess) e = hipMemsetAsync(vol, 0, nvox * sizeof(float), st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(vol, planes + (size_t)(nt - 1) * npix, npix * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  // fields zero except rho_xi = y^(nt-1) / (3 c0^2) on the plane; P^ = FFT of that pressure
+  k_fwd_init<NX, NY, NZ, V><<<NZ, NT, 0, st>>>(vol, B, tplanes, tplanes + npix, t, sc);
+  for (int n = 0; n < nt - 1; ++n) {
+    const bool last = n + 1 == nt - 1;
+    k_zgrad<NX, NY, NZ, V><<<D::NTILE, kThreadsZ, 0, st>>>(B.spec[0], B.spec[1], n == 0 ? 1 : 2, B.spec[0],
+                                                           B.spec[1], t, sc.inv_ntot);
+    k_fwd_u<NX, NY, NZ, V><<<2 * NZ, NT, 0, st>>>(B.spec[0], B.spec[1], B.spec[2], B.spec[3], B, t, sc, 0, ho.flags,
+                                                   next_epoch(ho));
+    k_zmul<NX, NY, NZ, V, false><<<dim3(D::NTILE, 3), kThreadsZ, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], t,
+                                                                           sc.inv_ntot);
+    k_fwd_rho<NX, NY, NZ, V, true><<<2 * NZ, NT, 0, st>>>(B.spec[2], B.spec[3], B.spec[1], B, B.spec[0], B.spec[1],
+                                                           tplanes, tplanes + npix, t, sc,
+                                                           planes + (size_t)(nt - 2 - n) * npix,
+                                                           last ? p_a : nullptr, last ? p_b : nullptr);
+  }
+  return hipGetLastError();
+}
+
 #define PAT_WAVE_IMPL(N)                                                            \
   {N, N, N, {&wave_forward<N, N, N, float2>, &wave_forward<N, N, N, double2>},     \
-   {&wave_adjoint<N, N, N, float2>, &wave_adjoint<N, N, N, double2>}}
+   {&wave_adjoint<N, N, N, float2>, &wave_adjoint<N, N, N, double2>},              \
+   {&wave_time_reversal<N, N, N, float2>, &wave_time_reversal<N, N, N, double2>}}
 
 static const WaveImpl kWaveImpls[] = {
     PAT_WAVE_IMPL(16),

@@ -4,9 +4,9 @@ trained on and judged by the plain TV-Bregman solver.
 K unrolled steps from p_0 = 0, each with a U-Net of its own (paper_1605_00133_amd.unet):
     z_k     = p_k - eta A^T C^T (C A p_k - f)         gradient step, eta = 1.8 / L (eq. BP, App. B)
     p_{k+1} = max(0, z_k + net_k([p_k, z_k]))
-The nets are trained one step after another (greedy): net_k maps the training
-set's (p_k, z_k) to the plain TV+Br reconstructions of the same data in mean
-squared error (Adam), then the next step starts from its outputs.
+The nets are trained one step after another (greedy): z_k + net_k([p_k, z_k])
+(before the clamp) is fitted to the plain TV+Br reconstructions of the same data
+in mean squared error (Adam), then the next step starts from its clamped outputs.
 
 Fallback: after the K steps the data residual ||C A p_K - f|| (FP64) is compared
 with that of plain TV+ FISTA run for the same number of operator pairs (K); if
@@ -90,14 +90,16 @@ class LearnedUNetRecon:
     def n_params(self):
         return sum(net.n_params for net in self.nets)
 
-    def step(self, k, p, z, keep=False):
-        """p_{k+1} and the net's input for [B, 1, N, N, N] tensors p, z."""
+    def step(self, k, p, z, keep=False, clamp=True):
+        """p_{k+1} = max(0, z + net_k([p, z])) for [B, 1, N, N, N] tensors p, z (clamp=False: the
+        value before the clamp, which training fits: through the clamp a step whose output has
+        gone negative everywhere gets no gradient and cannot recover)."""
         x = torch.empty((p.shape[0], 2) + tuple(p.shape[2:]), dtype=torch.float32, device=p.device)
         for b in range(p.shape[0]):
             nn.axpby(p[b, 0], None, 1.0, out=x[b, 0])
             nn.axpby(z[b, 0], None, 1.0, out=x[b, 1])
         out = self.nets[k].forward(x, keep=keep)
-        return nn.axpby(z, out, 1.0, 1.0, clamp0=True)
+        return nn.axpby(z, out, 1.0, 1.0, clamp0=clamp)
 
     def reconstruct(self, plan, f, L):
         """p_K for data f [Nt, M_c]; K operator pairs and K U-Net evaluations."""
@@ -234,9 +236,9 @@ def train(model, plan, fs, targets, L, epochs=40, batch=2, lr=1e-3, log=None):
                 pb = torch.cat([ps[i] for i in idx])
                 zb = torch.cat([zs[i] for i in idx])
                 tb = torch.stack([targets[i] for i in idx])[:, None].contiguous()
-                out = model.step(k, pb, zb, keep=True)
+                out = model.step(k, pb, zb, keep=True, clamp=False)
                 dout = torch.empty_like(out)
-                nn.mse(out, tb, grad=dout, mask0=True)
+                nn.mse(out, tb, grad=dout)
                 grads = net.backward(dout)
                 t_adam += 1
                 for name, wb in net.params.items():

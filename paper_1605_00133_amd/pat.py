@@ -63,9 +63,12 @@ SIGNATURES = {
     "pat_plan_destroy": (C.c_int, [_P]),
     "pat_plan_set_stream": (C.c_int, [_P, _P]),
     "pat_plan_set_fft_precision": (C.c_int, [_P, C.c_int32]),
+    "pat_plan_set_sensitivity": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "pat_plan_set_sound_speed": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "pat_plan_set_scheme": (C.c_int, [_P, C.c_int32]),
     "pat_forward": (C.c_int, [_P, _P, _P]),
     "pat_adjoint": (C.c_int, [_P, _P, _P]),
+    "pat_time_reversal": (C.c_int, [_P, _P, _P]),
     "pat_sample": (C.c_int, [_P, _P, _P]),
     "pat_sample_adjoint": (C.c_int, [_P, _P, _P]),
     "pat_tv_dual_floats": (C.c_size_t, [C.POINTER(pat_grid), C.c_int32]),
@@ -204,6 +207,27 @@ class Plan:
     def set_fft_precision(self, bits):
         _check(lib().pat_plan_set_fft_precision(self.handle, int(bits)))
 
+    def set_sensitivity(self, w):
+        """Per-pixel sensor sensitivity W_s (host array [ny][nx] or None for the ideal sensor)."""
+        if w is None:
+            _check(lib().pat_plan_set_sensitivity(self.handle, None))
+            return
+        w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+        if w.size != self.grid.nx * self.grid.ny:
+            raise ValueError(f"w must have {self.grid.nx * self.grid.ny} entries")
+        _check(lib().pat_plan_set_sensitivity(self.handle, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def set_sound_speed(self, c):
+        """Heterogeneous sound speed [nz][ny][nx] (host array, each <= c0) for data generation, or None."""
+        if c is None:
+            _check(lib().pat_plan_set_sound_speed(self.handle, None))
+            return
+        c = np.ascontiguousarray(c, dtype=np.float32).ravel()
+        g = self.grid
+        if c.size != g.nx * g.ny * g.nz:
+            raise ValueError(f"c must have {g.nx * g.ny * g.nz} entries")
+        _check(lib().pat_plan_set_sound_speed(self.handle, c.ctypes.data_as(C.POINTER(C.c_float))))
+
     def set_scheme(self, scheme):
         """PAT_SCHEME_LINE (default on cubic grids) or PAT_SCHEME_SLAB; the names "line"/"slab" work too."""
         if isinstance(scheme, str):
@@ -244,6 +268,12 @@ def pat_forward(plan, p0, f):
 def pat_adjoint(plan, f, p):
     plan.sync_stream()
     _check(lib().pat_adjoint(plan.handle, plan.check(f, plan.data_shape, "f"), plan.check(p, plan.vol_shape, "p")))
+
+
+def pat_time_reversal(plan, f, p):
+    plan.sync_stream()
+    _check(lib().pat_time_reversal(plan.handle, plan.check(f, plan.data_shape, "f"),
+                                   plan.check(p, plan.vol_shape, "p")))
 
 
 def pat_sample(plan, s, f):

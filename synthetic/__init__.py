@@ -10,8 +10,9 @@ same grid sizes stand in for them.
 """
 
 from .phantoms import (vessel_phantom, moving_vessel_frames, gaussian_volume, gaussian_data, gaussian_blob,
-                       lognormal_weights)
+                       lognormal_weights, sound_speed_field)
 from .configs import CONFIGS, make_grid_params
 
 __all__ = ["vessel_phantom", "moving_vessel_frames", "gaussian_volume", "gaussian_data", "gaussian_blob", "lognormal_weights",
+           "sound_speed_field",
            "CONFIGS", "make_grid_params"]

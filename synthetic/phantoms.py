@@ -147,3 +147,17 @@ def lognormal_weights(shape, sigma, seed):
     """w = exp(sigma X), X ~ N(0, 1) seeded (the paper's model of a spatially varying
     sensor sensitivity, sigma = 0.2, and of the noise level per sensor, sigma = 0.1)."""
     return np.exp(sigma * gaussian_data(shape, seed))
+
+
+def sound_speed_field(p0, c0, rel=0.05, seed=0, smooth=3.0):
+    """The perturbed sound speed of the paper's no-inverse-crime data (Sec. 5.3): a smooth
+    normalised Gaussian random field plus the normalised initial pressure, centred and
+    scaled so that its mean is 0 and its largest magnitude rel * c0, added to c0."""
+    from scipy.ndimage import gaussian_filter
+    p0 = np.asarray(p0, dtype=np.float64)
+    g = gaussian_filter(gaussian_data(p0.shape, seed), smooth)
+    g /= np.abs(g).max()
+    q = p0 / p0.max() if p0.max() > 0 else np.zeros_like(p0)
+    t = g + q
+    t -= t.mean()
+    return c0 + rel * c0 * t / np.abs(t).max()

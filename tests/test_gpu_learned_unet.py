@@ -1,0 +1,54 @@
+"""The learned reconstruction at the paper-scale workload against plain TV-Bregman.
+
+128^3, Nt = 740, 12.5 % scrambled-Hadamard sub-sampling (2048 of 16384 patterns),
+24-vessel phantoms with 1 % noise; the committed U-Net weights
+(paper_1605_00133_amd/weights/, trained by `python -m paper_1605_00133_amd.learned_unet`
+on TV+Br reconstructions of phantoms 1000-1023) on held-out phantoms 5004 and 5005
+(never used in training or in choosing the number of steps). For each, plain TV+Br
+(5 x 50 FISTA, lambda_Br = 10 lambda_TV+ from the discrepancy principle) logs PSNR
+and time per iteration; its target is its final PSNR minus 0.5 dB. The learned
+iteration (with its fallback check against plain FISTA at equal pairs running
+concurrently) must reach that target on average in at least 5x less wall time than
+TV+Br takes to reach it, with no fallback.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N_STEPS = 12
+
+
+def test_learned_unet_reaches_tvbr_within_half_db_5x_faster():
+    from paper_1605_00133_amd import pat as P
+    from paper_1605_00133_amd.learned_unet import (LearnedUNetRecon, evaluate_case, make_case, make_plan,
+                                                   summarize, weights_path)
+    from gpu_cases import to_dev
+    from synthetic import gaussian_volume
+    path = weights_path(128, "hadamard")
+    if not os.path.exists(path):
+        pytest.skip(f"weights {path} not present")
+    model = LearnedUNetRecon.load(path).truncated(N_STEPS)
+    plan = make_plan(128, "hadamard")
+    ref_plan = make_plan(128, "hadamard")
+    L = P.pat_power_iteration(plan, to_dev(gaussian_volume(plan.vol_shape, 8)), 10)
+    rows = []
+    for seed in (5004, 5005):
+        case = make_case(plan, seed, "hadamard")
+        rows.append(evaluate_case(model, plan, case, L, ref_plan=ref_plan))
+        r = rows[-1]
+        print(f"phantom {seed}: TV+Br {r['tvbr_final_db']:.2f} dB (target {r['tvbr_target_db']:.2f} dB at "
+              f"{r['tvbr_t_target_ms']:.0f} ms, all 250 iterations {r['tvbr_total_ms']:.0f} ms); learned "
+              f"{r['learned_db']:.2f} dB in {r['learned_ms']:.0f} ms: {r['db_vs_tvbr']:+.2f} dB, "
+              f"{r['speedup_vs_target_time']:.1f}x; fallback {r['fallback']}")
+    s = summarize(rows)
+    print({k: v for k, v in s.items()})
+    assert s["fallbacks"] == 0
+    assert s["mean_db_vs_tvbr"] >= -0.5
+    assert s["mean_speedup_vs_target_time"] >= 5.0
+    assert np.isfinite(s["mean_learned_db"])
+    ref_plan.close()
+    plan.close()

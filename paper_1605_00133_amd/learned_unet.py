@@ -16,7 +16,8 @@ the learned result.
 
 Workload (config of the learned update): the paper-scale grid (128^3, Nt = 740)
 with 12.5 % scrambled-Hadamard sub-sampling (2048 of 16384 patterns, seeds
-4/5), phantoms of 24 random vessels (training seeds 1000 + i, held-out 5000 + j,
+4/5), phantoms of 24 random vessels (training seeds 1000 + i, or a later block of
+seeds when training continues from saved weights; held-out 5000 + j,
 the benchmark phantom 1), 1 % Gaussian noise, TV+Br targets with
 lambda_Br = 10 lambda_TV+, lambda_TV+ = lam_tv_rel sigma sqrt(Nt M_c) (the
 discrepancy-principle calibration of synthetic.CONFIGS["paper"] scaled to each
@@ -256,9 +257,13 @@ def train(model, plan, fs, targets, L, epochs=40, batch=2, lr=1e-3, log=None):
 
 
 def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widths=(16, 32, 64), epochs=40,
-               batch=2, lr=1e-3, workers=2, save=None, eval_steps=None, log=None):
-    """Trains on n_train phantoms, evaluates on n_test held-out ones against plain TV+Br
-    (time to within 0.5 dB of its final PSNR vs the learned iteration's time, fallback included)."""
+               batch=2, lr=1e-3, workers=2, save=None, eval_steps=None, log=None, init=None, train_seed0=1000):
+    """Trains on n_train phantoms (seeds train_seed0 + i), evaluates on n_test held-out ones
+    (seeds 5000 + j) against plain TV+Br (time to within 0.5 dB of its final PSNR vs the learned
+    iteration's time, fallback included). init: a saved model whose first n_steps nets are the
+    starting point (training continued on further phantoms) instead of fresh nets."""
+    if train_seed0 < 0 or train_seed0 + n_train > 5000:
+        raise ValueError("training phantoms must not overlap the held-out seeds 5000 + j")
     from synthetic import gaussian_volume
     from .frames import reconstruct_all
     from .workload import target_time
@@ -266,7 +271,7 @@ def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widt
     plan = make_plan(n, sampling)
     x0 = torch.from_numpy(gaussian_volume(plan.vol_shape, 8).astype(np.float32)).to(dev)
     L = P.pat_power_iteration(plan, x0, 10)
-    train_cases = [make_case(plan, 1000 + i, sampling) for i in range(n_train)]
+    train_cases = [make_case(plan, train_seed0 + i, sampling) for i in range(n_train)]
     test_cases = [make_case(plan, 5000 + j, sampling) for j in range(n_test)]
     t0 = time.perf_counter()
     plans = [plan] + [make_plan(n, sampling) for _ in range(max(0, workers - 1))]
@@ -282,7 +287,13 @@ def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widt
         q.close()
     torch.cuda.synchronize()
     t_targets = time.perf_counter() - t0
-    model = LearnedUNetRecon(n_steps, widths, 0, dev)
+    if init:
+        model = LearnedUNetRecon.load(init, dev)
+        if model.n_steps < n_steps or model.widths != tuple(widths):
+            raise ValueError(f"{init}: {model.n_steps} steps of widths {model.widths}, asked for {n_steps} of {widths}")
+        model = model.truncated(n_steps)
+    else:
+        model = LearnedUNetRecon(n_steps, widths, 0, dev)
     t0 = time.perf_counter()
     losses = train(model, plan, [c["f"] for c in train_cases], targets, L, epochs=epochs, batch=batch, lr=lr,
                    log=log)
@@ -309,7 +320,8 @@ def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widt
             log(f"K = {k}: {json.dumps({a: b for a, b in summary[f'k{k}'].items() if a != 'cases'})}")
     summary.update({"n": n, "sampling": sampling, "n_train": n_train, "n_test": n_test, "n_steps": n_steps,
                     "widths": list(widths), "n_params": model.n_params, "epochs": epochs, "batch": batch, "lr": lr,
-                    "train_mse": losses, "targets_s": t_targets, "train_s": t_train, "L": L})
+                    "train_mse": losses, "targets_s": t_targets, "train_s": t_train, "L": L,
+                    "train_seed0": train_seed0, "init": os.path.basename(init) if init else None})
     ref_plan.close()
     plan.close()
     return summary
@@ -396,12 +408,14 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=2)
     ap.add_argument("--save", default=None, help="safetensors path ('default': the package's weights directory)")
     ap.add_argument("--eval-steps", default="", help="comma-separated step counts evaluated besides --steps")
+    ap.add_argument("--init", default=None, help="safetensors model to continue training from")
+    ap.add_argument("--train-seed0", type=int, default=1000, help="seed of the first training phantom")
     a = ap.parse_args(argv)
     widths = tuple(int(w) for w in a.widths.split(","))
     save = weights_path(a.n, a.sampling, widths) if a.save == "default" else a.save
     ev = [int(k) for k in a.eval_steps.split(",") if k.strip()]
     out = experiment(a.n, a.sampling, a.train, a.test, a.steps, widths, a.epochs, a.batch, a.lr, a.workers, save,
-                     ev, log=lambda m: print(m, file=sys.stderr, flush=True))
+                     ev, log=lambda m: print(m, file=sys.stderr, flush=True), init=a.init, train_seed0=a.train_seed0)
     print(json.dumps(out), flush=True)
 
 

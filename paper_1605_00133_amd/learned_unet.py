@@ -256,6 +256,17 @@ def train(model, plan, fs, targets, L, epochs=40, batch=2, lr=1e-3, log=None):
     return losses
 
 
+def initial_model(n_steps, widths, init=None, device="cuda:0"):
+    """Fresh nets (seed 0), or the first n_steps nets of the saved model init (same widths)."""
+    if not init:
+        return LearnedUNetRecon(n_steps, widths, 0, device)
+    model = LearnedUNetRecon.load(init, device)
+    if model.n_steps < n_steps or model.widths != tuple(widths):
+        raise ValueError(f"{init}: {model.n_steps} steps of widths {model.widths}, asked for {n_steps} of "
+                         f"{tuple(widths)}")
+    return model.truncated(n_steps)
+
+
 def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widths=(16, 32, 64), epochs=40,
                batch=2, lr=1e-3, workers=2, save=None, eval_steps=None, log=None, init=None, train_seed0=1000):
     """Trains on n_train phantoms (seeds train_seed0 + i), evaluates on n_test held-out ones
@@ -264,10 +275,11 @@ def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widt
     starting point (training continued on further phantoms) instead of fresh nets."""
     if train_seed0 < 0 or train_seed0 + n_train > 5000:
         raise ValueError("training phantoms must not overlap the held-out seeds 5000 + j")
+    dev = torch.device("cuda:0")
+    model = initial_model(n_steps, widths, init, dev)
     from synthetic import gaussian_volume
     from .frames import reconstruct_all
     from .workload import target_time
-    dev = torch.device("cuda:0")
     plan = make_plan(n, sampling)
     x0 = torch.from_numpy(gaussian_volume(plan.vol_shape, 8).astype(np.float32)).to(dev)
     L = P.pat_power_iteration(plan, x0, 10)
@@ -287,13 +299,6 @@ def experiment(n=128, sampling="hadamard", n_train=24, n_test=4, n_steps=8, widt
         q.close()
     torch.cuda.synchronize()
     t_targets = time.perf_counter() - t0
-    if init:
-        model = LearnedUNetRecon.load(init, dev)
-        if model.n_steps < n_steps or model.widths != tuple(widths):
-            raise ValueError(f"{init}: {model.n_steps} steps of widths {model.widths}, asked for {n_steps} of {widths}")
-        model = model.truncated(n_steps)
-    else:
-        model = LearnedUNetRecon(n_steps, widths, 0, dev)
     t0 = time.perf_counter()
     losses = train(model, plan, [c["f"] for c in train_cases], targets, L, epochs=epochs, batch=batch, lr=lr,
                    log=log)

@@ -339,7 +339,15 @@ def tv_bregman_reference(plan, case, L):
     _, log = tv_bregman(plan, case, L, p_ref=case["p0"])
     target, t_target, it = target_time(log["psnr"], log["t_ms"])
     return {"tvbr_final_db": float(log["psnr"][-1]), "tvbr_target_db": target, "tvbr_t_target_ms": t_target,
-            "tvbr_total_ms": float(log["t_ms"][-1]), "tvbr_target_iteration": it}
+            "tvbr_total_ms": float(log["t_ms"][-1]), "tvbr_target_iteration": it,
+            "_psnr": np.asarray(log["psnr"], dtype=np.float64), "_t_ms": np.asarray(log["t_ms"], dtype=np.float64)}
+
+
+def psnr_at_time(ref, t_ms):
+    """PSNR of the plain TV+Br run at wall time t_ms (its last logged iteration by then; -inf before
+    the first)."""
+    done = np.nonzero(ref["_t_ms"] <= t_ms)[0]
+    return float(ref["_psnr"][done[-1]]) if done.size else float("-inf")
 
 
 def evaluate_case(model, plan, case, L, ref=None, ref_plan=None):
@@ -348,8 +356,10 @@ def evaluate_case(model, plan, case, L, ref=None, ref_plan=None):
     _, info = reconstruct_with_fallback(model, plan, case["f"], L, case["lam_tv"], case["lam_br"], p_ref=case["p0"],
                                         ref_plan=ref_plan)
     row = {"seed": case["seed"], "n_steps": model.n_steps}
-    row.update(ref)
+    row.update({k: v for k, v in ref.items() if not k.startswith("_")})
+    tvbr_same_time = psnr_at_time(ref, info["ms"])
     row.update({"learned_db": info["psnr_db"], "learned_ms": info["ms"], "fallback": info["fallback"],
+                "tvbr_db_at_learned_time": tvbr_same_time, "gain_vs_tvbr_same_time": info["psnr_db"] - tvbr_same_time,
                 "residual_learned": info["residual_learned"],
                 "residual_plain_same_pairs": info["residual_plain_same_pairs"],
                 "db_vs_tvbr": info["psnr_db"] - ref["tvbr_final_db"],
@@ -360,7 +370,7 @@ def evaluate_case(model, plan, case, L, ref=None, ref_plan=None):
 
 def summarize(rows):
     keys = ("db_vs_tvbr", "speedup_vs_target_time", "speedup_vs_full_tvbr", "learned_db", "tvbr_final_db",
-            "learned_ms", "tvbr_t_target_ms")
+            "learned_ms", "tvbr_t_target_ms", "gain_vs_tvbr_same_time")
     out = {f"mean_{k}": float(np.mean([r[k] for r in rows])) for k in keys}
     out["min_db_vs_tvbr"] = float(np.min([r["db_vs_tvbr"] for r in rows]))
     out["min_speedup_vs_target_time"] = float(np.min([r["speedup_vs_target_time"] for r in rows]))
@@ -388,6 +398,8 @@ def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64)):
            "residual_learned": info["residual_learned"],
            "residual_plain_same_pairs": info["residual_plain_same_pairs"],
            "db_vs_tvbr_final": info["psnr_db"] - curve["final_psnr_db"],
+           "tvbr_db_at_learned_time": psnr_at_time({"_psnr": np.asarray(curve["psnr"], dtype=np.float64),
+                                                    "_t_ms": np.asarray(curve["t_ms"], dtype=np.float64)}, info["ms"]),
            "speedup_vs_tvbr_target_time": curve["t_target_ms"] / info["ms"],
            "speedup_vs_tvbr_total": curve["total_ms"] / info["ms"],
            "within_0p5_db": bool(info["psnr_db"] >= curve["target_psnr_db"])}

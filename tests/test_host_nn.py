@@ -71,3 +71,12 @@ def test_continued_training_checks_before_any_device_work(tmp_path):
     with pytest.raises(ValueError):
         initial_model(2, (4, 8, 16), path, "cpu")      # other widths
     assert initial_model(2, (4, 8, 8), None, "cpu").n_steps == 2
+
+
+def test_psnr_at_time_takes_last_logged_iteration():
+    import numpy as np
+    from paper_1605_00133_amd.learned_unet import psnr_at_time
+    ref = {"_psnr": np.array([10.0, 12.0, 15.0]), "_t_ms": np.array([100.0, 200.0, 300.0])}
+    assert psnr_at_time(ref, 250.0) == 12.0
+    assert psnr_at_time(ref, 300.0) == 15.0
+    assert psnr_at_time(ref, 99.0) == float("-inf")

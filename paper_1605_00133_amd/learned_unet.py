@@ -23,6 +23,12 @@ lambda_Br = 10 lambda_TV+, lambda_TV+ = lam_tv_rel sigma sqrt(Nt M_c) (the
 discrepancy-principle calibration of synthetic.CONFIGS["paper"] scaled to each
 phantom's noise level), 5 x 50 FISTA iterations, 50 PDHG steps.
 
+The committed weights (weights/unet_n128_hadamard_w16-32-64.safetensors, 8 steps)
+came from three runs of 24 phantoms each:
+    --steps 10 --epochs 90 --lr 1e-3                               (seeds 1000-1023)
+    --init <that> --train-seed0 1024 --epochs 70 --lr 5e-4          (seeds 1024-1047)
+    --init <that> --train-seed0 1048 --steps 8 --epochs 30 --lr 2e-4 (seeds 1048-1071)
+
 Every operation of the learned iteration and of its training runs in libpat:
 pat_forward / pat_adjoint, pat_axpby, the U-Net's convolution, resampling and
 add kernels, pat_mse and pat_adam_step. Weights are saved with safetensors

@@ -9,11 +9,18 @@
   (sampled z-slices incl. the sensor plane and a z-PML slice, and the norms) within
   1e-5, and against central differences along 16 random directions d (seeded
   N(0, 1) fields smoothed by a Gaussian of 2 voxels and scaled to unit RMS per
-  voxel, so that d is not nearly orthogonal to the gradient) with eps = 1e-3: L is
-  quadratic, so the central difference equals the directional derivative up to the
-  rounding of the FP32 data (tolerance 1e-4). The
-  backward is A^T itself, so it keeps no tape of the 560 steps and needs no
-  checkpoints.
+  voxel). L is quadratic, so the central difference has no truncation error at any
+  eps; what limits it is the rounding of the FP32 data. An evaluation of L from data
+  f = C A x with per-element errors e_i carries the error sum_i r_i e_i (r = f - b),
+  of standard deviation about delta ||r o f|| when |e_i| ~ delta |f_i|; two
+  evaluations divided by 2 eps give a central-difference error of about
+  sqrt(2) delta ||r o f|| / (2 eps). With delta = 1e-5 (the tolerance of A) and four
+  standard deviations this is the bound asserted at eps = 1e-3 (the configuration's
+  step). The directions are nearly orthogonal to the gradient (|cos| ~ 1e-4-1e-3),
+  so at that step the measured differences are 3e-5-2e-3 of <grad, d>; at eps = 1 the
+  same noise is a thousand times smaller and the central difference must agree
+  within 1e-4 (measured 3e-7-3e-6). The backward is A^T itself, so it keeps no tape
+  of the 560 steps and needs no checkpoints.
 """
 
 import os
@@ -88,15 +95,25 @@ def test_differentiation_96_batch4():
         with torch.no_grad():
             return 0.5 * float(((measure(plan, v) - b).double() ** 2).sum())
 
+    with torch.no_grad():
+        f = measure(plan, p).double()
+        rf = float(((f - b.double()) * f).norm())
+    delta = TOL_OP
     from scipy.ndimage import gaussian_filter
-    eps = 1e-3
-    worst = 0.0
+    worst = {1e-3: 0.0, 1.0: 0.0}
     for k in range(16):
         dh = np.stack([gaussian_filter(gaussian_data((n, n, n), 100 + 4 * k + i), 2.0) for i in range(4)])
         d = to_dev(dh / np.sqrt(np.mean(dh * dh)))
-        fd = (L(p + eps * d) - L(p - eps * d)) / (2 * eps)
         an = float((grad.double() * d.double()).sum())
-        worst = max(worst, abs(fd - an) / abs(an))
-        print(f"direction {k}: central difference {fd:.8e}, autograd {an:.8e}")
-        assert abs(fd - an) <= 1e-4 * abs(an)
-    print(f"worst relative difference over 16 directions: {worst:.2e}")
+        for eps in (1e-3, 1.0):
+            fd = (L(p + eps * d) - L(p - eps * d)) / (2 * eps)
+            bound = 4.0 * np.sqrt(2.0) * delta * rf / (2 * eps)
+            worst[eps] = max(worst[eps], abs(fd - an) / abs(an))
+            print(f"direction {k}, eps {eps:g}: central difference {fd:.8e}, autograd {an:.8e}, "
+                  f"difference {abs(fd - an):.2e} (noise bound {bound:.2e})")
+            if eps == 1.0:
+                assert abs(fd - an) <= 1e-4 * abs(an)
+            else:
+                assert abs(fd - an) <= bound
+    print(f"||r o f|| = {rf:.4e}; worst relative difference over 16 directions: eps 1e-3 {worst[1e-3]:.2e}, "
+          f"eps 1 {worst[1.0]:.2e}")

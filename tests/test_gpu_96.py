@@ -63,8 +63,7 @@ def test_operator_96_matches_oracle(scheme):
 
 def _fixture():
     path = os.path.join(GOLDEN, "grad96_points.npz")
-    if not os.path.exists(path):
-        pytest.skip(f"fixture {path} not generated")
+    assert os.path.exists(path), f"committed fixture {path} is missing"
     return np.load(path)
 
 

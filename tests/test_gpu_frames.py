@@ -68,7 +68,10 @@ def test_captured_scan_matches_oracle_and_eager():
     from synthetic import gaussian_data, moving_vessel_frames
     sizes = [32, 16, 32, 16, 16]
     iters, n_prox, L = 5, 20, 4.0
-    seqs = {n: moving_vessel_frames((n, n, n), 4, len(sizes), 6, 1.0, 2.0, 3) for n in (16, 32)}
+    # a quarter voxel per frame: at 16^3 the interior is a few voxels wide, and a faster
+    # motion carries the vessels out of it within two frames (empty data, 0/0 errors)
+    seqs = {n: moving_vessel_frames((n, n, n), 4, len(sizes), 6, 1.0, 2.0, 3, shift=0.25) for n in (16, 32)}
+    assert all(float(v.max()) > 0.1 for n in seqs for v in seqs[n])
     plans, fs, lams, refs = [], [], [], []
     for t, n in enumerate(sizes):
         nt = 740 * n // 128

@@ -25,10 +25,9 @@ TOL_OP = 1e-5
 TOL_RECON = 1e-4
 
 
-def _fixture(case):
-    path = os.path.join(GOLDEN, f"op128_{case}.npz")
-    if not os.path.exists(path):
-        pytest.skip(f"fixture {path} not generated")
+def _fixture(case, prefix="op128_"):
+    path = os.path.join(GOLDEN, f"{prefix}{case}.npz")
+    assert os.path.exists(path), f"committed fixture {path} is missing"
     return np.load(path)
 
 
@@ -88,7 +87,7 @@ def test_reconstruction_128(kind):
     included) and the norm of the reconstruction within 1e-4.
     """
     from paper_1605_00133_amd import pat as Pb
-    fx = _fixture(f"recon128_{kind}")
+    fx = _fixture(f"recon128_{kind}", prefix="")
     plan = _plan(kind)
     p0 = vessel_phantom((N, N, N), P, 24, 1.0, 4.0, 1)
     f = empty(plan.data_shape)

@@ -35,8 +35,7 @@ def test_learned_unet_against_tvbr_time_to_target():
     from gpu_cases import to_dev
     from synthetic import gaussian_volume
     path = weights_path(128, "hadamard")
-    if not os.path.exists(path):
-        pytest.skip(f"weights {path} not present")
+    assert os.path.exists(path), f"committed weights {path} are missing"
     model = LearnedUNetRecon.load(path).truncated(N_STEPS)
     plan = make_plan(128, "hadamard")
     ref_plan = make_plan(128, "hadamard")

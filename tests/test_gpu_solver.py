@@ -26,8 +26,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 def _fixture(name):
     path = os.path.join(GOLDEN, f"{name}.npz")
-    if not os.path.exists(path):
-        pytest.skip(f"fixture {path} not generated")
+    assert os.path.exists(path), f"committed fixture {path} is missing"
     return np.load(path)
 
 

@@ -238,6 +238,20 @@ pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p,
 pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t n_iter,
                              int32_t n_prox, int32_t bc, double* log);
 
+/* Iterations it0 .. it0 + n_iter - 1 of the same loop (eq. VarReg/TV+, App. B),
+ * so that one reconstruction can be enqueued, or captured, in several parts:
+ * it0 = 0 is pat_fista_enqueue; it0 > 0 continues from the iterate, its
+ * predecessor, the extrapolated point, their residuals and the prox dual that
+ * the call for iterations 0 .. it0 - 1 left in the plan's workspace, with the
+ * same f, lambda, L, n_prox and bc. The parts together give p bit for bit as
+ * one call of it0 + n_iter iterations. No other pat_reconstruct,
+ * pat_fista_enqueue(_from) or pat_power_iteration call may run on the plan
+ * between the parts (they use the same workspace); pat_forward, pat_adjoint and
+ * pat_psnr may. log: NULL or device FP64 [n_iter][2] for these iterations.
+ * p receives the latest iterate after every part. */
+pat_status pat_fista_enqueue_from(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t it0,
+                                  int32_t n_iter, int32_t n_prox, int32_t bc, double* log);
+
 /* Thresholded PSNR of p against p_ref (eq. PSNR) over the non-PML interior with
  * z >= 1: negatives clipped, both scaled by their maximum, values < 0.1 zeroed.
  * p, p_ref: device volumes. Host result; syncs. +Inf when identical. */

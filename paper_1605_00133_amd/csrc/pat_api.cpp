@@ -934,16 +934,22 @@ pat_status pat_reconstruct(pat_plan* plan, const float* f, float* p, const pat_r
   return PAT_OK;
 }
 
-pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t n_iter,
-                             int32_t n_prox, int32_t bc, double* log) {
+// Iterations it0 .. it0 + n_iter - 1 of the TV+ FISTA loop of pat_reconstruct (n_outer = 1,
+// restart off). The iterate, its predecessor, the extrapolated point, their residuals and the
+// prox dual live in the plan's workspace; it0 = 0 starts from x = 0, it0 > 0 continues from
+// what the previous call left there (the pointer roles alternate every iteration and t follows
+// its recurrence, so both are recomputed from it0).
+static pat_status fista_enqueue_range(pat_plan* plan, const char* who, const float* f, float* p, double lambda,
+                                      double L, int32_t it0, int32_t n_iter, int32_t n_prox, int32_t bc, double* log) {
   PAT_TRY(check_plan(plan));
-  if (!f || !p) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: null pointer");
-  if (!(L > 0) || !std::isfinite(L)) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: L must be > 0");
-  if (!(lambda >= 0) || !std::isfinite(lambda)) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: lambda must be >= 0");
-  if (n_iter < 0 || n_prox < 0) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: iteration counts out of range");
-  if (bc != 0 && bc != 1) return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: bc must be 0 or 1");
+  if (!f || !p) return set_error(PAT_ERR_INVALID, "%s: null pointer", who);
+  if (!(L > 0) || !std::isfinite(L)) return set_error(PAT_ERR_INVALID, "%s: L must be > 0", who);
+  if (!(lambda >= 0) || !std::isfinite(lambda)) return set_error(PAT_ERR_INVALID, "%s: lambda must be >= 0", who);
+  if (it0 < 0 || n_iter < 0 || n_prox < 0 || n_iter > (1 << 20) || it0 > (1 << 20))
+    return set_error(PAT_ERR_INVALID, "%s: iteration counts out of range", who);
+  if (bc != 0 && bc != 1) return set_error(PAT_ERR_INVALID, "%s: bc must be 0 or 1", who);
   if (overlaps(p, vol_bytes(plan), f, data_bytes(plan)))
-    return set_error(PAT_ERR_INVALID, "pat_fista_enqueue: f and p overlap");
+    return set_error(PAT_ERR_INVALID, "%s: f and p overlap", who);
   DeviceGuard dg(plan->device);
   hipStream_t st = plan->stream;
   const long nv = vol_n(plan), nd = data_n(plan);
@@ -954,12 +960,20 @@ pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double la
   float* tmp = plan->data[DAT_TMP];
   // the same arithmetic, in the same order, as pat_reconstruct with n_outer = 1 and restart = 0,
   // but every operand stays on the device: kernels only, no copies, no host synchronisation
-  PAT_TRY_HIP(launch_fill(xp, 0.f, nv, st));
-  PAT_TRY_HIP(launch_fill(plan->dual, 0.f, (long)n_dual(plan->g, bc), st));
-  PAT_TRY_HIP(launch_scale(f, rp, -1.f, nd, st));               // x0 = 0: r_prev = -f
-  PAT_TRY_HIP(launch_fill(y, 0.f, nv, st));
-  PAT_TRY_HIP(launch_scale(rp, ry, 1.f, nd, st));
   double t = 1.0;
+  if (it0 == 0) {
+    PAT_TRY_HIP(launch_fill(xp, 0.f, nv, st));
+    PAT_TRY_HIP(launch_fill(plan->dual, 0.f, (long)n_dual(plan->g, bc), st));
+    PAT_TRY_HIP(launch_scale(f, rp, -1.f, nd, st));               // x0 = 0: r_prev = -f
+    PAT_TRY_HIP(launch_fill(y, 0.f, nv, st));
+    PAT_TRY_HIP(launch_scale(rp, ry, 1.f, nd, st));
+  } else {
+    for (int it = 0; it < it0; ++it) t = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    if (it0 % 2) {
+      std::swap(x, xp);
+      std::swap(rx, rp);
+    }
+  }
   for (int it = 0; it < n_iter; ++it) {
     PAT_TRY(op_adjoint(plan, ry, g));
     PAT_TRY_HIP(launch_axpy(y, g, v, (float)(-eta), nv, st));
@@ -980,6 +994,16 @@ pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double la
   }
   PAT_TRY_HIP(launch_scale(xp, p, 1.f, nv, st));
   return PAT_OK;
+}
+
+pat_status pat_fista_enqueue(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t n_iter,
+                             int32_t n_prox, int32_t bc, double* log) {
+  return fista_enqueue_range(plan, "pat_fista_enqueue", f, p, lambda, L, 0, n_iter, n_prox, bc, log);
+}
+
+pat_status pat_fista_enqueue_from(pat_plan* plan, const float* f, float* p, double lambda, double L, int32_t it0,
+                                  int32_t n_iter, int32_t n_prox, int32_t bc, double* log) {
+  return fista_enqueue_range(plan, "pat_fista_enqueue_from", f, p, lambda, L, it0, n_iter, n_prox, bc, log);
 }
 
 pat_status pat_profile_begin(pat_plan* plan, int32_t kernel_id, int32_t max_launches) {

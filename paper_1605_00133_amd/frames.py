@@ -107,47 +107,93 @@ def reconstruct_all(plans, fs, ps, lams, Ls, workers=None, warm=True, **kwargs):
     return outs
 
 
+# Largest graph captured here, in kernel nodes (estimated by graph_nodes). Graphs of up to
+# about 60 000 nodes (two iterations of a 24-frame scan at 64^3-128^3) were built and replayed
+# many times; building one of about 900 000 (thirty iterations of that scan in one graph)
+# ended the process with a host segmentation fault whose cause in this code is not known, so
+# larger graphs are refused and a long scan is captured as a sequence of graphs instead.
+MAX_GRAPH_NODES = 1 << 16
+
+
+def graph_nodes(nts, n_iter, n_prox):
+    """Upper estimate of the kernel launches that n_iter TV+ FISTA iterations of frames with these
+    Nt enqueue (line scheme): per iteration one forward and one adjoint application (Nt step
+    launches each plus set-up), n_prox dual and primal prox launches, and a few vector kernels."""
+    return sum(5 + int(n_iter) * (2 * int(nt) + 2 * int(n_prox) + 24) for nt in nts)
+
+
+def max_iters_per_graph(nts, n_prox, budget=MAX_GRAPH_NODES):
+    """The most iterations of all frames that one graph may hold (at least 1)."""
+    per = graph_nodes(nts, 1, n_prox) - graph_nodes(nts, 0, n_prox)
+    return max(1, (budget - graph_nodes(nts, 0, n_prox)) // per)
+
+
 class CapturedScan:
-    """Every frame's TV+ FISTA (n_iter iterations from 0, no restart) captured as ONE
-    HIP graph (torch.cuda.CUDAGraph over pat_fista_enqueue): frame k runs on branch
-    k % branches of the graph, the branches join at its end, and one replay()
-    launches the whole scan. Plans must use the line scheme (the slab scheme refuses
-    capture). Outputs ps[k] and the per-iteration logs [n_iter, 2] (sum r^2, TV) are
+    """Every frame's TV+ FISTA (n_iter iterations from 0, no restart) captured in HIP graphs
+    (torch.cuda.CUDAGraph over pat_fista_enqueue_from): each graph holds `iters_per_graph`
+    iterations of ALL frames, frame k on branch k % branches (the branches join at the
+    graph's end); replay() launches the graphs in order on the current stream. With
+    iters_per_graph = n_iter (the default) the whole scan is one graph; a graph of more than
+    MAX_GRAPH_NODES estimated launches is refused. The parts continue each other exactly, so
+    the result does not depend on the split. Plans must use the line scheme (the slab scheme
+    refuses capture). Outputs ps[k] and the per-iteration logs [n_iter, 2] (sum r^2, TV) are
     overwritten by each replay; data are read from fs[k] at replay time."""
 
-    def __init__(self, plans, fs, lams, Ls, n_iter, n_prox=50, branches=4, order=None):
+    def __init__(self, plans, fs, lams, Ls, n_iter, n_prox=50, branches=4, order=None, iters_per_graph=None):
         dev = plans[0].device
         self.plans, self.fs, self.n_iter = plans, fs, int(n_iter)
         self.order = list(range(len(plans))) if order is None else list(order)
         self.branches = max(1, min(int(branches), len(plans)))
+        self.n_prox = int(n_prox)
+        k_graph = max(1, self.n_iter) if iters_per_graph is None else int(iters_per_graph)
+        if not 1 <= k_graph <= max(1, self.n_iter):
+            raise ValueError(f"iters_per_graph must be in [1, {self.n_iter}]")
+        nts = [pl.grid.nt for pl in plans]
+        self.nodes_per_graph = graph_nodes(nts, k_graph, self.n_prox)
+        if self.nodes_per_graph > MAX_GRAPH_NODES:
+            raise ValueError(f"a graph of {k_graph} iterations of these frames would hold about "
+                             f"{self.nodes_per_graph} kernel launches, more than the {MAX_GRAPH_NODES} supported; "
+                             f"use iters_per_graph <= {max_iters_per_graph(nts, self.n_prox)}")
+        self.parts = [(i0, min(k_graph, self.n_iter - i0)) for i0 in range(0, self.n_iter, k_graph)]
         self.ps = [torch.empty(pl.vol_shape, dtype=torch.float32, device=dev) for pl in plans]
         self.logs = [torch.zeros((self.n_iter, 2), dtype=torch.float64, device=dev) for _ in plans]
         self.args = [(float(lams[k]), float(Ls[k])) for k in range(len(plans))]
-        self.n_prox = int(n_prox)
         side = [torch.cuda.Stream(device=dev) for _ in range(self.branches)]   # default priority
 
-        def enqueue_all():
+        def enqueue(i0, m):
             cur = torch.cuda.current_stream(dev)
             for s in side:
                 s.wait_stream(cur)
             for j, k in enumerate(self.order):
                 with torch.cuda.stream(side[j % self.branches]):
                     lam, L = self.args[k]
-                    P.pat_fista_enqueue(self.plans[k], self.fs[k], self.ps[k], lam, L, self.n_iter, self.n_prox,
-                                        "dirichlet", self.logs[k])
+                    P.pat_fista_enqueue_from(self.plans[k], self.fs[k], self.ps[k], lam, L, i0, m, self.n_prox,
+                                             "dirichlet", self.logs[k][i0:i0 + m])
             for s in side:
                 cur.wait_stream(s)
 
-        enqueue_all()                       # eager run: first launches and code loading outside the capture
+        for i0, m in self.parts:            # eager run: first launches and code loading outside the capture
+            enqueue(i0, m)
         torch.cuda.synchronize(dev)
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            enqueue_all()
+        self.graphs = []
+        for i0, m in self.parts:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                enqueue(i0, m)
+            self.graphs.append(g)
         for pl in plans:
             pl.sync_stream()                # back to the caller's stream for eager use
 
+    @property
+    def graph(self):
+        """The single graph of a scan captured in one part."""
+        if len(self.graphs) != 1:
+            raise AttributeError(f"this scan is captured in {len(self.graphs)} graphs")
+        return self.graphs[0]
+
     def replay(self):
-        self.graph.replay()
+        for g in self.graphs:
+            g.replay()
 
     def energies(self):
         """Per frame, the energy 1/2 ||C A x - f||^2 + lambda TV(x) after each iteration (host arrays)."""
@@ -245,10 +291,11 @@ def _scan_setup(sizes, n_frames, rate, seed, lam_rel=None):
 
 def captured_dynamic_scan(sizes=(64, 96, 128), n_frames=24, iters=30, rate=8, n_prox=50, seed=1, tune=True,
                           cache=None, log=print):
-    """The dynamic (4D) scan as one HIP graph: all frames' TV+ FISTA (`iters` iterations,
-    no restart) captured once (CapturedScan, branches and order from autotune_scan) and
-    launched with one replay; against the same iterations run eagerly frame after frame
-    (pat_reconstruct, restart off: equal bit for bit). Returns rates and PSNRs."""
+    """The dynamic (4D) scan in HIP graphs: all frames' TV+ FISTA (`iters` iterations, no
+    restart) captured once (CapturedScan, branches and order from autotune_scan), as many
+    iterations of all frames per graph as MAX_GRAPH_NODES allows, and launched by one
+    replay; against the same iterations run eagerly frame after frame (pat_reconstruct,
+    restart off: equal bit for bit). Returns rates and PSNRs."""
     import time
 
     import numpy as np
@@ -260,7 +307,9 @@ def captured_dynamic_scan(sizes=(64, 96, 128), n_frames=24, iters=30, rate=8, n_
         choice, timings = autotune_scan(plans, fs, lams, Ls, iters, n_prox, cache=cache, log=log)
     else:
         choice, timings = {"branches": 4, "frame_order": list(range(n_frames)), "order": "largest_first"}, []
-    scan = CapturedScan(plans, fs, lams, Ls, iters, n_prox, choice["branches"], choice["frame_order"])
+    k_graph = min(iters, max_iters_per_graph([pl.grid.nt for pl in plans], n_prox))
+    scan = CapturedScan(plans, fs, lams, Ls, iters, n_prox, choice["branches"], choice["frame_order"],
+                        iters_per_graph=k_graph)
     scan.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -281,6 +330,7 @@ def captured_dynamic_scan(sizes=(64, 96, 128), n_frames=24, iters=30, rate=8, n_
     out = {"frames": n_frames, "sizes": sorted(set(frame_n)), "frame_sizes": frame_n, "iters": iters,
            "n_prox": n_prox, "graph_s": t_graph, "frames_per_s_graph": n_frames / t_graph, "eager_s": t_eager,
            "frames_per_s_eager": n_frames / t_eager, "speedup": t_eager / t_graph, "identical_to_eager": same,
+           "graphs": len(scan.graphs), "iters_per_graph": k_graph, "graph_nodes_estimate": scan.nodes_per_graph,
            "autotune": {k: v for k, v in choice.items() if k != "frame_order"}, "autotune_timings": timings,
            "psnr_db_mean": float(np.mean(psnr)), "psnr_db_min": float(np.min(psnr))}
     del scan

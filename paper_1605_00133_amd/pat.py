@@ -78,6 +78,8 @@ SIGNATURES = {
     "pat_reconstruct": (C.c_int, [_P, _P, _P, C.POINTER(pat_recon_params), C.POINTER(pat_recon_report)]),
     "pat_psnr": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
     "pat_fista_enqueue": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P]),
+    "pat_fista_enqueue_from": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                         C.c_int32, _P]),
     "pat_make_rsp_mask": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_int32)]),
     "pat_make_shd_pattern": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]),
@@ -365,16 +367,31 @@ def pat_reconstruct(plan, f, p, lam, L, n_outer=1, n_inner=10, n_prox=50, bc="di
     return out
 
 
+def _enqueue_log(plan, log, n_iter):
+    if log is None:
+        return None
+    t = plan.torch
+    if log.dtype != t.float64 or log.device != plan.device or not log.is_contiguous() or \
+            tuple(log.shape) != (int(n_iter), 2):
+        raise ValueError(f"log must be a contiguous float64 tensor [{n_iter}, 2] on {plan.device}")
+    return C.c_void_p(log.data_ptr())
+
+
 def pat_fista_enqueue(plan, f, p, lam, L, n_iter=30, n_prox=50, bc="dirichlet", log=None):
     """Enqueues n_iter TV+ FISTA iterations (no restart, no host synchronisation: capturable in a
     HIP graph). log: None or a float64 device tensor [n_iter, 2] (sum r^2, TV per iteration)."""
     plan.sync_stream()
-    lp = None
-    if log is not None:
-        t = plan.torch
-        if log.dtype != t.float64 or log.device != plan.device or not log.is_contiguous() or \
-                tuple(log.shape) != (int(n_iter), 2):
-            raise ValueError(f"log must be a contiguous float64 tensor [{n_iter}, 2] on {plan.device}")
-        lp = C.c_void_p(log.data_ptr())
+    lp = _enqueue_log(plan, log, n_iter)
     _check(lib().pat_fista_enqueue(plan.handle, plan.check(f, plan.data_shape, "f"), plan.check(p, plan.vol_shape, "p"),
                                    float(lam), float(L), int(n_iter), int(n_prox), BC[bc], lp))
+
+
+def pat_fista_enqueue_from(plan, f, p, lam, L, it0, n_iter, n_prox=50, bc="dirichlet", log=None):
+    """Iterations it0 .. it0 + n_iter - 1 of the loop of pat_fista_enqueue, continuing from the state
+    the call for iterations 0 .. it0 - 1 left in the plan (same f, lam, L, n_prox, bc): the parts give
+    the one-call result bit for bit. log: None or float64 [n_iter, 2] for these iterations."""
+    plan.sync_stream()
+    lp = _enqueue_log(plan, log, n_iter)
+    _check(lib().pat_fista_enqueue_from(plan.handle, plan.check(f, plan.data_shape, "f"),
+                                        plan.check(p, plan.vol_shape, "p"), float(lam), float(L), int(it0),
+                                        int(n_iter), int(n_prox), BC[bc], lp))

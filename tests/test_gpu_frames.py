@@ -105,3 +105,51 @@ def test_captured_scan_matches_oracle_and_eager():
     assert all(torch.equal(a, b) for a, b in zip(first, scan.ps))
     e = scan.energies()
     assert all(np.all(np.isfinite(x)) for x in e)
+
+
+def test_enqueue_in_parts_equals_one_call_and_chunked_capture():
+    """pat_fista_enqueue_from: iterations 0-1, 2-4 and 5-6 enqueued as three parts give the
+    7-iteration pat_fista_enqueue result and log bit for bit (odd and even part boundaries);
+    a CapturedScan split into graphs of 2 iterations replays to the single-graph result bit
+    for bit, twice."""
+    import numpy as np
+    import torch
+
+    from paper_1605_00133_amd import pat as P
+    from paper_1605_00133_amd.frames import CapturedScan
+    from synthetic import moving_vessel_frames
+    n, nt, iters, n_prox, L = 32, 185, 7, 10, 4.0
+    smp = oracle_sampling("points", n)
+    plan = gpu_plan(n, nt, smp, pml=4)
+    p0 = to_dev(moving_vessel_frames((n, n, n), 4, 1, 6, 1.0, 2.0, 5, shift=0.25)[0])
+    f = empty(plan.data_shape)
+    P.pat_forward(plan, p0, f)
+    f += 0.01 * float(f.abs().max()) * to_dev(gaussian_data(plan.data_shape, 9))
+    lam = 2e-3 * 0.01 * float(f.abs().max()) * np.sqrt(f.numel())
+    one, parts = empty(plan.vol_shape), empty(plan.vol_shape)
+    log1 = torch.zeros((iters, 2), dtype=torch.float64, device="cuda:0")
+    log2 = torch.zeros((iters, 2), dtype=torch.float64, device="cuda:0")
+    P.pat_fista_enqueue(plan, f, one, lam, L, iters, n_prox, "dirichlet", log1)
+    for i0, m in ((0, 2), (2, 3), (5, 2)):
+        P.pat_fista_enqueue_from(plan, f, parts, lam, L, i0, m, n_prox, "dirichlet", log2[i0:i0 + m])
+    torch.cuda.synchronize()
+    print(f"parts vs one call: equal {torch.equal(one, parts)}, logs equal {torch.equal(log1, log2)}")
+    assert torch.equal(one, parts) and torch.equal(log1, log2)
+
+    plans = [plan, gpu_plan(16, 93, oracle_sampling("points", 16), pml=4)]
+    p1 = to_dev(moving_vessel_frames((16, 16, 16), 4, 1, 6, 1.0, 2.0, 6, shift=0.25)[0])
+    f1 = empty(plans[1].data_shape)
+    P.pat_forward(plans[1], p1, f1)
+    whole = CapturedScan(plans, [f, f1], [lam, lam], [L, L], iters, n_prox, branches=2)
+    split = CapturedScan(plans, [f, f1], [lam, lam], [L, L], iters, n_prox, branches=2, iters_per_graph=2)
+    assert len(whole.graphs) == 1 and len(split.graphs) == 4
+    whole.replay()
+    torch.cuda.synchronize()
+    ref = [p.clone() for p in whole.ps]
+    assert torch.equal(ref[0], one)
+    for _ in range(2):
+        split.replay()
+        torch.cuda.synchronize()
+        same = [torch.equal(a, b) for a, b in zip(ref, split.ps)]
+        print(f"split graphs vs one graph: {same}")
+        assert all(same)

@@ -28,3 +28,23 @@ def test_vessels_are_those_of_vessel_phantom():
     a = moving_vessel_frames((32, 32, 32), 8, 1, 6, 1.0, 2.0, 1, shift=0.0, pulse=0.0)[0]
     b = vessel_phantom((32, 32, 32), 8, 6, 1.0, 2.0, 1)
     assert np.abs(a - b).max() < 0.5 and np.abs(a - b).sum() < 0.05 * b.sum()
+
+
+def test_graph_node_budget_and_split():
+    """The node estimate grows with Nt, n_prox and iterations; the 24-frame scan at 64^3-128^3
+    (Nt = 370 / 555 / 740) fits two iterations of all frames in one graph and not thirty, and
+    CapturedScan refuses an oversized graph before touching any device."""
+    from types import SimpleNamespace
+    import pytest
+    from paper_1605_00133_amd.frames import MAX_GRAPH_NODES, CapturedScan, graph_nodes, max_iters_per_graph
+    nts = [740] * 9 + [555] * 7 + [370] * 8
+    assert graph_nodes([740], 1, 50) == 5 + 2 * 740 + 100 + 24
+    assert graph_nodes(nts, 2, 50) <= MAX_GRAPH_NODES < graph_nodes(nts, 3, 50)
+    assert max_iters_per_graph(nts, 50) == 2
+    assert max_iters_per_graph([16], 20) > 30
+    assert max_iters_per_graph([10 ** 6], 50) == 1        # never below one iteration
+    plans = [SimpleNamespace(device="cpu", grid=SimpleNamespace(nt=nt), vol_shape=(8, 8, 8)) for nt in nts]
+    with pytest.raises(ValueError, match="iters_per_graph <= 2"):
+        CapturedScan(plans, [None] * 24, [1.0] * 24, [1.0] * 24, 30, 50)
+    with pytest.raises(ValueError):
+        CapturedScan(plans, [None] * 24, [1.0] * 24, [1.0] * 24, 30, 50, iters_per_graph=31)

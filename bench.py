@@ -228,8 +228,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the hot path has no multi-GPU mode "
-              "(independent problems shard trivially, see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the hot path has no multi-GPU mode (independent problems "
+              "such as the frames of a scan would go one per GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

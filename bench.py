@@ -23,8 +23,9 @@ sampling mode's rates; 2 and 4 independent problems at once (4 x 0.5 GB is
 above the 256 MB last-level cache); with patterned interrogation (the learned
 update's workload) the time-to-target curve of plain TV+Br (5 x 50, PSNR and
 wall time per iteration) and, when trained weights are present, the learned
-reconstruction against it; the FP64 oracle timed on the host (all cores and
-one core).
+reconstruction against it, on this phantom and on held-out phantoms 5004...
+(--learned-phantoms) against their own TV+Br runs; the FP64 oracle timed on the
+host (all cores and one core).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -221,6 +222,8 @@ def main():
     ap.add_argument("--cpu-steps-1", type=int, default=3, help="time steps of the one-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--learned-phantoms", type=int, default=3,
+                    help="held-out phantoms (seeds 5004...) the learned reconstruction is also compared on")
     ap.add_argument("--other-sampling", type=int, default=1, help="also time the other sampling mode (0: skip)")
     ap.add_argument("--concurrent", default="2,4",
                     help="comma-separated counts of independent problems timed at once ('' or 0: skip)")
@@ -328,7 +331,8 @@ def main():
             f"({c['target_psnr_db']:.2f} dB) at {c['t_target_ms']:.0f} ms (iteration {c['target_iteration']})")
         try:
             from paper_1605_00133_amd.learned_unet import bench_learned
-            ttt["learned"] = bench_learned(prob_t, c, log=log)
+            seeds = tuple(5004 + i for i in range(max(0, args.learned_phantoms)))
+            ttt["learned"] = bench_learned(prob_t, c, log=log, extra_seeds=seeds)
         except (ImportError, FileNotFoundError) as e:
             ttt["learned"] = None
             log(f"learned: not run ({e})")

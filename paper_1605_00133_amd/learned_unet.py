@@ -384,10 +384,11 @@ def summarize(rows):
     return out
 
 
-def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64)):
+def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64), extra_seeds=(5004, 5005, 5006)):
     """The learned iteration (first n_steps steps of the committed weights) on the benchmark's problem
-    (a held-out phantom), against the plain TV+Br curve `curve` of the same problem. Raises
-    FileNotFoundError without weights."""
+    (a held-out phantom), against the plain TV+Br curve `curve` of the same problem, and on the
+    held-out phantoms `extra_seeds` (make_case) against their own TV+Br runs; the means are over all
+    of them. Raises FileNotFoundError without weights."""
     path = weights_path(prob["n"], prob["sampling"], widths)
     if not os.path.exists(path):
         raise FileNotFoundError(path)
@@ -398,6 +399,8 @@ def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64)):
     reconstruct_with_fallback(model, plan, f, L, prob["lam_tv"], prob["lam_br"], ref_plan=ref_plan)   # warm-up
     _, info = reconstruct_with_fallback(model, plan, f, L, prob["lam_tv"], prob["lam_br"], p_ref=prob["p0"],
                                         ref_plan=ref_plan)
+    rows = [evaluate_case(model, plan, make_case(plan, seed, prob["sampling"]), L, ref_plan=ref_plan)
+            for seed in extra_seeds]
     ref_plan.close()
     out = {"weights": os.path.relpath(path, os.path.dirname(PKG)), "n_steps": model.n_steps,
            "n_params": model.n_params, "psnr_db": info["psnr_db"], "ms": info["ms"], "fallback": info["fallback"],
@@ -413,6 +416,20 @@ def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64)):
         log(f"learned ({model.n_steps} steps): {info['psnr_db']:.2f} dB in {info['ms']:.0f} ms "
             f"({out['db_vs_tvbr_final']:+.2f} dB vs TV+Br, {out['speedup_vs_tvbr_target_time']:.1f}x faster than its "
             f"time to target), fallback {info['fallback']}")
+    if rows:
+        dbs = [out["db_vs_tvbr_final"]] + [r["db_vs_tvbr"] for r in rows]
+        sps = [out["speedup_vs_tvbr_target_time"]] + [r["speedup_vs_target_time"] for r in rows]
+        out["held_out"] = [{k: r[k] for k in ("seed", "tvbr_final_db", "tvbr_t_target_ms", "learned_db", "learned_ms",
+                                              "db_vs_tvbr", "speedup_vs_target_time", "tvbr_db_at_learned_time",
+                                              "fallback")} for r in rows]
+        out["phantoms"] = len(dbs)
+        out["mean_db_vs_tvbr_final"] = float(np.mean(dbs))
+        out["mean_speedup_vs_tvbr_target_time"] = float(np.mean(sps))
+        out["fallbacks"] = int(info["fallback"]) + sum(int(r["fallback"]) for r in rows)
+        out["mean_within_0p5_db"] = bool(out["mean_db_vs_tvbr_final"] >= -0.5)
+        if log:
+            log(f"learned over {len(dbs)} phantoms: " + ", ".join(f"{d:+.2f} dB / {v:.1f}x" for d, v in zip(dbs, sps))
+                + f"; mean {out['mean_db_vs_tvbr_final']:+.2f} dB, {out['mean_speedup_vs_tvbr_target_time']:.1f}x")
     return out
 
 

@@ -145,19 +145,48 @@ def fista_rate(P, torch, prob, steps, warmup, n_prox):
     return 0.5 * (n_fwd + n_adj), elapsed, out
 
 
-def operator_rate(P, torch, prob, pairs=3):
+def operator_rate(P, torch, prob, pairs=10, per_pair=None):
+    """Operator-only pairs/s over `pairs` back-to-back pairs (host clock); with a dict per_pair,
+    also each pair's duration by HIP events on the current stream (median, min ms)."""
     plan, dev = prob["plan"], prob["f"].device
     g = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     ftmp = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
     P.pat_forward(plan, prob["p0"], ftmp)
     P.pat_adjoint(plan, ftmp, g)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(pairs + 1)]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(pairs):
+    ev[0].record()
+    for i in range(pairs):
         P.pat_forward(plan, prob["p0"], ftmp)
         P.pat_adjoint(plan, ftmp, g)
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    return pairs / (time.perf_counter() - t)
+    rate = pairs / (time.perf_counter() - t)
+    if per_pair is not None:
+        ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(pairs))
+        per_pair.update({"pairs": pairs, "median_ms": round(float(np.median(ms)), 3), "min_ms": round(ms[0], 3),
+                         "max_ms": round(ms[-1], 3)})
+    return rate
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second, GB/s) of an nbytes buffer, the
+    practical HBM ceiling of this GPU; median of reps timed copies."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        out.append(2.0 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src, dst
+    return float(np.median(out))
 
 
 def concurrent_rate(P, torch, prob, K, reps=2):
@@ -255,7 +284,11 @@ def main():
     log(f"timed: {args.steps} FISTA steps in {elapsed:.3f} s, {pairs} pairs, restarts {int((flags > 0).sum())}, "
         f"PSNR after them {out['psnr'][-1]:.2f} dB")
 
-    op_pairs_s = operator_rate(P, torch, prob)
+    pair_ms = {}
+    op_pairs_s = operator_rate(P, torch, prob, per_pair=pair_ms)
+    copy_GBps = copy_ceiling(torch)
+    log(f"operator pairs: {op_pairs_s:.2f}/s, per pair median {pair_ms['median_ms']:.2f} ms (min {pair_ms['min_ms']:.2f}); "
+        f"device copy ceiling {copy_GBps:.0f} GB/s")
 
     # ---- live per-kernel timing of one pair with HIP events on the plan's stream ----------
     dev = prob["f"].device
@@ -284,7 +317,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"],
-                "frac_of_3d_fft_step_bytes": round(survey_bytes / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                "frac_of_3d_fft_step_bytes": round(survey_bytes / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "frac_of_copy_ceiling": round(dk["GBps"] / copy_GBps, 4)}
 
     err = fp64_error(P, torch, prob)
     if err:
@@ -364,7 +398,8 @@ def main():
                    "lambda_tv": prob["lam_tv"], "lambda_br": prob["lam_br"], "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "operator_pairs_per_s": round(op_pairs_s, 4),
+        "operator_pairs_per_s": round(op_pairs_s, 4), "operator_pair_ms": pair_ms,
+        "copy_ceiling_GBps": round(copy_GBps, 1),
         "fp64_error": err,
         "other_sampling": other,
         "concurrent": concurrent,

@@ -118,7 +118,8 @@ pat_status pat_axpby(const float* x, const float* y, float* out, int64_t n, floa
  * *loss = mean((a - t)^2) as an FP64 device scalar (block partials summed in a
  * fixed order), and, if grad is not NULL, grad = 2 (a - t) / n, set to 0 where
  * a <= 0 when mask0 != 0 (the gradient through an output clamp max(0, .)).
- * workspace: device, >= pat_mse_workspace_bytes(). */
+ * workspace: device, >= pat_mse_workspace_bytes(), 8-byte aligned like loss;
+ * n in [1, 2^40]. */
 size_t pat_mse_workspace_bytes(void);
 pat_status pat_mse(const float* a, const float* t, float* grad, int64_t n, int32_t mask0, double* loss,
                    void* workspace, size_t workspace_bytes, void* stream);

@@ -62,8 +62,8 @@ __global__ __launch_bounds__(kT) void k_spread8(const float* __restrict__ coarse
   fine[i] = scale * coarse[((c * nz2 + z / 2) * ny2 + y / 2) * nx2 + x / 2];
 }
 
-__global__ __launch_bounds__(kT) void k_add_act(const float* __restrict__ a, const float* __restrict__ b,
-                                                float* __restrict__ y, long n, int relu) {
+// y may alias a or b (one element per thread, read before written): no __restrict__
+__global__ __launch_bounds__(kT) void k_add_act(const float* a, const float* b, float* y, long n, int relu) {
   const long i = (long)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   float v = a[i];
@@ -71,8 +71,9 @@ __global__ __launch_bounds__(kT) void k_add_act(const float* __restrict__ a, con
   y[i] = relu ? fmaxf(v, 0.f) : v;
 }
 
-__global__ __launch_bounds__(kT) void k_axpby(const float* __restrict__ x, const float* __restrict__ yv,
-                                              float* __restrict__ out, long n, float alpha, float beta, int clamp0) {
+// out may alias x or yv, as above
+__global__ __launch_bounds__(kT) void k_axpby(const float* x, const float* yv, float* out, long n, float alpha,
+                                              float beta, int clamp0) {
   const long i = (long)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   float v = alpha * x[i];
@@ -203,10 +204,12 @@ size_t pat_mse_workspace_bytes(void) { return kLossBlocks * sizeof(double); }
 
 pat_status pat_mse(const float* a, const float* t, float* grad, int64_t n, int32_t mask0, double* loss,
                    void* workspace, size_t workspace_bytes, void* stream) {
-  if (n < 1) return pat::set_error(PAT_ERR_INVALID, "pat_mse: n must be >= 1");
+  if (n < 1 || n > (1L << 40)) return pat::set_error(PAT_ERR_INVALID, "pat_mse: n must be in [1, 2^40]");
   if (!a || !t || !loss) return pat::set_error(PAT_ERR_INVALID, "pat_mse: null pointer");
   if (!workspace || workspace_bytes < pat_mse_workspace_bytes())
     return pat::set_error(PAT_ERR_NOMEM, "pat_mse: workspace of %zu bytes needed", pat_mse_workspace_bytes());
+  if ((reinterpret_cast<uintptr_t>(workspace) | reinterpret_cast<uintptr_t>(loss)) & 7u)
+    return pat::set_error(PAT_ERR_INVALID, "pat_mse: workspace and loss must be 8-byte aligned");
   const long nb0 = (n + kT - 1) / kT;
   const int nb = (int)(nb0 < kLossBlocks ? nb0 : kLossBlocks);
   double* part = static_cast<double*>(workspace);

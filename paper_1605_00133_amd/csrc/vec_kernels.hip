@@ -274,9 +274,10 @@ __global__ __launch_bounds__(kThreadsVec) void k_sum2(const float* __restrict__ 
   if (i < n) out[i] = a[i] + a[i + stride];
 }
 
-// out[t][i] = w[i] * a[t][i] for the plane series [nt][npix] (sensor sensitivity, eq. FwdSenVar)
-__global__ __launch_bounds__(kThreadsVec) void k_scale_pixels(const float* __restrict__ a, const float* __restrict__ w,
-                                                             float* __restrict__ out, long n, int npix) {
+// out[t][i] = w[i] * a[t][i] for the plane series [nt][npix] (sensor sensitivity, eq. FwdSenVar);
+// out may be a (in place: one element per thread, read before written), so a and out are not __restrict__
+__global__ __launch_bounds__(kThreadsVec) void k_scale_pixels(const float* a, const float* __restrict__ w, float* out,
+                                                             long n, int npix) {
   const long i = (long)blockIdx.x * kThreadsVec + threadIdx.x;
   if (i < n) out[i] = w[i % npix] * a[i];
 }

@@ -170,23 +170,29 @@ def operator_rate(P, torch, prob, pairs=10, per_pair=None):
     return rate
 
 
-def copy_ceiling(torch, nbytes=1 << 30, reps=5):
-    """Device-to-device copy rate (read + write bytes per second, GB/s) of an nbytes buffer, the
-    practical HBM ceiling of this GPU; median of reps timed copies."""
+def copy_ceiling(P, torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rates (read + write bytes per second, GB/s) of an nbytes buffer: torch's
+    copy and the library's copy kernel (pat_copy_probe), median of reps timed copies each;
+    the larger is the practical HBM ceiling of this GPU. Returns {"torch": .., "pat_copy_probe": ..}."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     src.fill_(1.0)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    out = []
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        dst.copy_(src)
-        b.record()
-        torch.cuda.synchronize()
-        out.append(2.0 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    rates = {}
+    for name, fn in (("torch", lambda: dst.copy_(src)), ("pat_copy_probe", lambda: P.pat_copy_probe(src, dst))):
+        fn()
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(2.0 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+        rates[name] = round(float(np.median(out)), 1)
+    if not torch.equal(src, dst):
+        raise RuntimeError("copy probe: destination differs from source")
     del src, dst
-    return float(np.median(out))
+    return rates
 
 
 def concurrent_rate(P, torch, prob, K, reps=2):
@@ -286,9 +292,10 @@ def main():
 
     pair_ms = {}
     op_pairs_s = operator_rate(P, torch, prob, per_pair=pair_ms)
-    copy_GBps = copy_ceiling(torch)
+    copy_rates = copy_ceiling(P, torch)
+    copy_GBps = max(copy_rates.values())
     log(f"operator pairs: {op_pairs_s:.2f}/s, per pair median {pair_ms['median_ms']:.2f} ms (min {pair_ms['min_ms']:.2f}); "
-        f"device copy ceiling {copy_GBps:.0f} GB/s")
+        f"device copy: torch {copy_rates['torch']:.0f} GB/s, pat_copy_probe {copy_rates['pat_copy_probe']:.0f} GB/s")
 
     # ---- live per-kernel timing of one pair with HIP events on the plan's stream ----------
     dev = prob["f"].device
@@ -399,7 +406,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "operator_pairs_per_s": round(op_pairs_s, 4), "operator_pair_ms": pair_ms,
-        "copy_ceiling_GBps": round(copy_GBps, 1),
+        "copy_ceiling_GBps": round(copy_GBps, 1), "copy_rates_GBps": copy_rates,
         "fp64_error": err,
         "other_sampling": other,
         "concurrent": concurrent,

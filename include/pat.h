@@ -289,6 +289,15 @@ pat_status pat_profile_end(pat_plan* plan, double* total_ms, int32_t* launches);
  * plane). *name points to static storage. */
 pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char** name, double* bytes_per_launch);
 
+/* Diagnostics: dst = src for nbytes on `stream` (a hipStream_t; NULL: the
+ * default stream) with a plain copy kernel (each block copies 16 KB of
+ * consecutive 16-byte words, four loads in flight per thread): the practical
+ * HBM copy rate of the device, against which the propagator's bandwidth is
+ * reported. src,
+ * dst: device, 16-byte aligned, not overlapping; nbytes a multiple of 16 in
+ * [0, 2^40]. Asynchronous; errors of the arguments are returned at once. */
+pat_status pat_copy_probe(const void* src, void* dst, int64_t nbytes, void* stream);
+
 /* Host-only index generators (no GPU needed). SplitMix64(seed) drives a
  * Durstenfeld Fisher-Yates shuffle of [0, n_pix) with unbiased rejection draws.
  * rSP: the first mc entries, sorted ascending. sHd: perm = shuffle(seed), rows =

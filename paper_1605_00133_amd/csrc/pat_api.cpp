@@ -1067,6 +1067,19 @@ pat_status pat_profile_end(pat_plan* plan, double* total_ms, int32_t* launches) 
   return PAT_OK;
 }
 
+pat_status pat_copy_probe(const void* src, void* dst, int64_t nbytes, void* stream) {
+  if (nbytes < 0 || nbytes % 16 || nbytes > (int64_t(1) << 40))
+    return set_error(PAT_ERR_INVALID, "pat_copy_probe: nbytes must be a multiple of 16 in [0, 2^40]");
+  if (nbytes == 0) return PAT_OK;
+  if (!src || !dst) return set_error(PAT_ERR_INVALID, "pat_copy_probe: null pointer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u)
+    return set_error(PAT_ERR_INVALID, "pat_copy_probe: src and dst must be 16-byte aligned");
+  if (overlaps(src, (size_t)nbytes, dst, (size_t)nbytes))
+    return set_error(PAT_ERR_INVALID, "pat_copy_probe: src and dst overlap");
+  PAT_TRY_HIP(launch_copy_probe(src, dst, (long)(nbytes / 16), static_cast<hipStream_t>(stream)));
+  return PAT_OK;
+}
+
 pat_status pat_kernel_info(const pat_plan* plan, int32_t kernel_id, const char** name, double* bytes_per_launch) {
   static const char* kNames[K_COUNT] = {"k_zgrad", "k_fwd_u",   "k_zmul<div>", "k_fwd_rho", "k_zmul<grad>",
                                         "k_adj_u", "k_zdiv_sum", "k_adj_rho",   "k_line<fwd>", "k_line<adj>"};

@@ -24,6 +24,8 @@ hipError_t launch_scale(const float* a, float* out, float s, long n, hipStream_t
 // out[i] = a[i] + a[i + stride], i < n
 hipError_t launch_sum2(const float* a, long stride, float* out, long n, hipStream_t st);
 hipError_t launch_fill(float* out, float v, long n, hipStream_t st);
+// dst = src, n16 words of 16 bytes (both 16-byte aligned, no overlap)
+hipError_t launch_copy_probe(const void* src, void* dst, long n16, hipStream_t st);
 // out[t][i] = w[i] a[t][i], t < nt, i < npix (may be in place)
 hipError_t launch_scale_pixels(const float* a, const float* w, float* out, int nt, int npix, hipStream_t st);
 

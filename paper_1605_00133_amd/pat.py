@@ -86,6 +86,7 @@ SIGNATURES = {
     "pat_profile_begin": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "pat_profile_end": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "pat_kernel_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_double)]),
+    "pat_copy_probe": (C.c_int, [_P, _P, C.c_int64, _P]),
     "pat_last_error": (C.c_char_p, []),
     "pat_version": (C.c_char_p, []),
 }
@@ -316,6 +317,19 @@ def pat_power_iteration(plan, x0, n_iter):
     out = C.c_double()
     _check(lib().pat_power_iteration(plan.handle, plan.check(x0, plan.vol_shape, "x0"), int(n_iter), C.byref(out)))
     return out.value
+
+
+def pat_copy_probe(src, dst):
+    """dst = src (contiguous CUDA tensors of the same byte size, a multiple of 16) with the library's
+    copy kernel, on the current stream: the HBM copy-rate probe of the bench."""
+    import torch
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst must have the same size in bytes")
+    stream = torch.cuda.current_stream(dst.device).cuda_stream
+    _check(lib().pat_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), int(nb), C.c_void_p(stream)))
 
 
 PAT_K_COUNT = 10

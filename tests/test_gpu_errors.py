@@ -98,3 +98,25 @@ def test_plan_workspace_too_small_or_misaligned():
     assert not h.value
     assert lib.pat_plan_create(C.byref(g), C.byref(smp), None, C.c_void_p(base), need, C.byref(h)) == 0
     assert lib.pat_plan_destroy(h) == 0
+
+
+def test_copy_probe_copies_and_rejects_bad_arguments():
+    """The bench's copy kernel: exact copies of sizes that are and are not a multiple of a block's
+    4 x 256 16-byte words (the guarded tail), nothing written past nbytes, and the documented
+    argument errors."""
+    import torch
+    from paper_1605_00133_amd import pat as P
+    for n in (4, 4 * 1023, 4 * 4096 * 7 + 12, 1 << 22):
+        src = torch.arange(n, dtype=torch.float32, device="cuda")
+        dst = torch.full((n + 4,), -1.0, device="cuda")
+        P.pat_copy_probe(src, dst[:n])
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:n], src) and bool((dst[n:] == -1.0).all())
+    lib = P.lib()
+    a = torch.zeros(64, device="cuda")
+    b = torch.zeros(64, device="cuda")
+    for args in ((a.data_ptr(), b.data_ptr(), 20), (a.data_ptr() + 4, b.data_ptr(), 16),
+                 (a.data_ptr(), a.data_ptr() + 16, 64), (0, b.data_ptr(), 16), (a.data_ptr(), b.data_ptr(), -16)):
+        st = lib.pat_copy_probe(C.c_void_p(args[0]), C.c_void_p(args[1]), args[2], None)
+        assert st == 1, args                                             # PAT_ERR_INVALID
+    assert lib.pat_copy_probe(None, None, 0, None) == 0                  # nothing to copy: PAT_OK

@@ -1,6 +1,12 @@
-"""Independent problems run concurrently (paper_1605_00133_amd.frames) give
-bit-identical results to the same problems run one after the other: the
-kernels are deterministic and the problems share nothing."""
+"""Frames of a dynamic scan (paper_1605_00133_amd.frames).
+
+* Independent problems run concurrently give bit-identical results to the same
+  problems run one after the other: the kernels are deterministic and the
+  problems share nothing.
+* All frames captured in HIP graphs (CapturedScan) match the FP64 oracle's FISTA
+  frame by frame and equal the eager runs bit for bit, over repeated replays.
+* pat_fista_enqueue_from: a reconstruction enqueued in parts equals one call bit
+  for bit, and a scan captured as several graphs equals the one-graph capture."""
 
 import numpy as np
 import pytest

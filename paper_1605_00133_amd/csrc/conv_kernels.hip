@@ -146,19 +146,28 @@ constexpr int kTileX = 16, kTileY = 4;                     // output tile of one
 constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2;
 constexpr int kMaxCpadLds = 64;                            // larger layers use k_conv3d
 constexpr int kMaxCt = 4;                                  // output-channel tiles per block
+constexpr int kConvPlanes = 2;                             // output z-planes per block
 
-// The input halo of a 16 x 4 x 1 output tile sits in LDS as bfloat16, channels
-// innermost ([dz][y][x][cpad]): the A operand of a lane (8 channels at one tap
-// of its voxel, v_mfma_f32_16x16x32_bf16: lane l holds row l & 15, K entries
-// 8 (l >> 4) .. + 7) is one 16-byte LDS read. The packed B operand is one
-// 16-byte global read per lane, the same for every block (cache-resident).
+// The input halo of a 16 x 4 x ZB output tile sits in LDS as bfloat16, channels
+// innermost ([dz][y][x][cpad], ZB + 2 planes): the A operand of a lane (8
+// channels at one tap of its voxel, v_mfma_f32_16x16x32_bf16: lane l holds row
+// l & 15, K entries 8 (l >> 4) .. + 7) is one 16-byte LDS read. The packed B
+// operand is one 16-byte global read per lane, the same for every block
+// (cache-resident), and serves the ZB output planes of the block. Staging the
+// halo (global loads, conversion, LDS stores) is a large share of the block's
+// time: ZB planes per block stage (ZB + 2) / ZB planes per output plane, and
+// each thread stages 8 channels of a voxel with one 16-byte LDS store.
+template <int ZB>
 __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x, const short* __restrict__ wb,
                                                     const float* __restrict__ bias, float* __restrict__ y, int nb,
                                                     int cin, int cout, int nz, int ny, int nx, int relu, int cpad,
-                                                    int nch, int ctiles, int xtiles, int ytiles, int cgroups) {
+                                                    int nch, int ctiles, int xtiles, int ytiles, int cgroups,
+                                                    int ztiles) {
+  constexpr int kPlanes = ZB + 2;
   extern __shared__ __align__(16) unsigned char smem[];
   short* xs = reinterpret_cast<short*>(smem);
-  const int halo = 3 * kHaloY * kHaloX * cpad;
+  const int plane = kHaloY * kHaloX * cpad;
+  const int halo = kPlanes * plane;
   int* qoff = reinterpret_cast<int*>(xs + halo);           // halo is a multiple of 8 elements
   const int nq = kTaps * cpad / 8;
   long t = blockIdx.x;
@@ -168,8 +177,8 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   t /= ytiles;
   const int cg = (int)(t % cgroups);
   t /= cgroups;
-  const int zz = (int)(t % nz);
-  const int b = (int)(t / nz);
+  const int z0 = (int)(t % ztiles) * ZB;
+  const int b = (int)(t / ztiles);
   const int x0 = xt * kTileX, y0 = yt * kTileY;
   const int tid = threadIdx.x;
   for (int j = tid; j < nq; j += 256) {
@@ -178,35 +187,49 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
   }
   const long vol = (long)nz * ny * nx;
   const float* xb = x + (long)b * cin * vol;
-  for (int i = tid; i < halo; i += 256) {                  // x fastest: coalesced global reads
-    const int hx = i % kHaloX;
-    int rest = i / kHaloX;
-    const int hy = rest % kHaloY;
-    rest /= kHaloY;
-    const int hz = rest % 3, c = rest / 3;
-    const int gz = zz + hz - 1, gy = y0 + hy - 1, gx = x0 + hx - 1;
-    float v = 0.f;
-    if (c < cin && gz >= 0 && gz < nz && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
-      v = xb[c * vol + ((long)gz * ny + gy) * nx + gx];
-    xs[((hz * kHaloY + hy) * kHaloX + hx) * cpad + c] = bf16_rne(v);
+  // one item = 8 channels of one halo voxel, channel group fastest: consecutive lanes write
+  // consecutive 16-byte LDS slots (one conflict-free store per item), and each of the 8 global
+  // loads of an item reads consecutive x across the lanes of a channel group
+  const int cq8 = cpad / 8;
+  const int nitems = kPlanes * kHaloY * kHaloX * cq8;
+  for (int i = tid; i < nitems; i += 256) {
+    const int cq = i % cq8, vx = i / cq8;
+    const int hx = vx % kHaloX;
+    const int rest = vx / kHaloX;
+    const int hy = rest % kHaloY, hz = rest / kHaloY;
+    const int gz = z0 + hz - 1, gy = y0 + hy - 1, gx = x0 + hx - 1;
+    bf16x8 pk = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (gz >= 0 && gz < nz && gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+      const float* src = xb + (long)(8 * cq) * vol + ((long)gz * ny + gy) * nx + gx;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (8 * cq + k < cin) pk[k] = bf16_rne(src[(long)k * vol]);
+    }
+    *reinterpret_cast<bf16x8*>(xs + vx * cpad + 8 * cq) = pk;
   }
   __syncthreads();
   const int lane = tid & 63, wy = tid >> 6, r = lane & 15, q = lane >> 4;
   const int ct0 = cg * kMaxCt, nct = min(kMaxCt, ctiles - ct0);
   const short* arow = xs + (wy * kHaloX + r) * cpad;
-  f32x4 acc[kMaxCt];
+  f32x4 acc[kMaxCt][ZB];
 #pragma unroll
-  for (int c = 0; c < kMaxCt; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < kMaxCt; ++c)
+#pragma unroll
+    for (int p = 0; p < ZB; ++p) acc[c][p] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int ch = 0; ch < nch; ++ch) {
     const int j = ch * 4 + q;
-    const bf16x8 a = j < nq ? *reinterpret_cast<const bf16x8*>(arow + qoff[j]) : zero;
+    bf16x8 a[ZB];
+#pragma unroll
+    for (int p = 0; p < ZB; ++p) a[p] = j < nq ? *reinterpret_cast<const bf16x8*>(arow + p * plane + qoff[j]) : zero;
 #pragma unroll
     for (int c = 0; c < kMaxCt; ++c) {
       if (c < nct) {
         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wb + (((long)(ct0 + c) * nch + ch) * 64 + lane) * 8);
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, bv),
-                                                         acc[c], 0, 0, 0);
+#pragma unroll
+        for (int p = 0; p < ZB; ++p)
+          acc[c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a[p]),
+                                                              __builtin_bit_cast(bf16v8, bv), acc[c][p], 0, 0, 0);
       }
     }
   }
@@ -217,13 +240,18 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const float* __restrict__ x,
     const int co = (ct0 + c) * 16 + r;
     if (c < nct && co < cout) {
       const float bb = bias ? bias[co] : 0.f;
-      float* yrow = y + ((long)b * cout + co) * vol + ((long)zz * ny + yo) * nx;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int xo = x0 + 4 * q + i;
-        if (xo < nx) {
-          const float v = acc[c][i] + bb;
-          yrow[xo] = relu ? fmaxf(v, 0.f) : v;
+      for (int p = 0; p < ZB; ++p) {
+        if (z0 + p < nz) {
+          float* yrow = y + ((long)b * cout + co) * vol + ((long)(z0 + p) * ny + yo) * nx;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int xo = x0 + 4 * q + i;
+            if (xo < nx) {
+              const float v = acc[c][p][i] + bb;
+              yrow[xo] = relu ? fmaxf(v, 0.f) : v;
+            }
+          }
         }
       }
     }
@@ -514,15 +542,21 @@ pat_status launch_conv(const char* who, const float* x, const float* w, const fl
     const int cpad = conv_cpad(cin), nch = conv_nch(cin), ctiles = (cout + 15) / 16;
     const int xtiles = (nx + kTileX - 1) / kTileX, ytiles = (ny + kTileY - 1) / kTileY;
     const int cgroups = (ctiles + kMaxCt - 1) / kMaxCt;
-    const long blocks = (long)nb * nz * cgroups * ytiles * xtiles;
+    // two output planes per block (four staged planes, at most 55 KB of LDS): 92 VGPRs. Four
+    // planes per block need 168 (three waves per SIMD) and ran 20-35 % slower; one plane per
+    // block stages three planes per output plane instead of two.
+    constexpr int zb = kConvPlanes;
+    const int ztiles = (nz + zb - 1) / zb;
+    const long blocks = (long)nb * ztiles * cgroups * ytiles * xtiles;
     if (blocks > 0x7fffffffL) return pat::set_error(PAT_ERR_INVALID, "%s: grid too large", who);
     short* wb = (short*)workspace;
     const long npack = (long)ctiles * nch * 512;
     hipLaunchKernelGGL(k_conv3d_pack_weights<TW>, dim3((unsigned)((npack + 255) / 256)), dim3(256), 0, st, w, wb, cin,
                        cout, cpad, nch, ctiles);
-    const size_t lds = (size_t)3 * kHaloY * kHaloX * cpad * sizeof(short) + (size_t)(kTaps * cpad / 8) * sizeof(int);
-    hipLaunchKernelGGL(k_conv3d_lds, dim3((unsigned)blocks), dim3(256), lds, st, x, wb, bias, y, nb, cin, cout, nz, ny,
-                       nx, relu, cpad, nch, ctiles, xtiles, ytiles, cgroups);
+    const size_t lds = (size_t)(zb + 2) * kHaloY * kHaloX * cpad * sizeof(short) +
+                       (size_t)(kTaps * cpad / 8) * sizeof(int);
+    hipLaunchKernelGGL(k_conv3d_lds<zb>, dim3((unsigned)blocks), dim3(256), lds, st, x, wb, bias, y, nb, cin, cout, nz,
+                       ny, nx, relu, cpad, nch, ctiles, xtiles, ytiles, cgroups, ztiles);
     return launched(who);
   }
   const int xtiles = (nx + 15) / 16, ctiles = (cout + 15) / 16;

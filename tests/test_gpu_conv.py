@@ -31,6 +31,7 @@ CASES = [  # (batch, c_in, c_out, nz, ny, nx)
     (1, 24, 24, 6, 7, 33),
     (1, 70, 5, 4, 5, 18),      # forward on the unpacked kernel (more than 64 input channels)
     (1, 5, 70, 3, 4, 17),      # five output-channel tiles: two channel groups per tile
+    (1, 64, 32, 5, 6, 20),     # 64 input channels: two output planes per block, odd nz
 ]
 
 

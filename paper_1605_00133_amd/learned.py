@@ -9,9 +9,13 @@ are trained one step after another (greedy): net_k maps the training set's z_k
 to the targets, the plain TV(+Bregman) reconstructions of the same data, in mean
 squared error; the next step then starts from the trained step's output.
 
-The operator, the convolutions and their gradients, and Adam run in libpat's
-kernels. The residual add, the output ReLU and the squared-error loss are the
-torch elementwise operations that glue them together.
+The operator, the convolutions and their gradients, Adam and, in the learned
+iteration itself (reconstruct, CapturedReconstruct), every elementwise step
+(residual, gradient step, the input stacking, the correction and its clamp:
+pat_axpby) run in libpat's kernels. Training differentiates the step with torch
+autograd (the convolutions' backward is libpat's); there the same elementwise
+steps and the squared-error loss are torch operations, with the same FP32
+arithmetic as pat_axpby.
 """
 
 import math
@@ -50,18 +54,25 @@ class LearnedUpdate:
         return nn.conv3d(h, w3, b3)
 
     def step(self, k, p, z):
-        """p_{k+1} from [B, 1, nz, ny, nx] iterates p and gradient steps z."""
-        return torch.clamp_min(z + self.net(k, torch.cat([p, z], dim=1).contiguous()), 0.0)
+        """p_{k+1} from [B, 1, nz, ny, nx] iterates p and gradient steps z. Under autograd (training)
+        the elementwise glue is torch's; otherwise pat_axpby (the same FP32 operations)."""
+        if torch.is_grad_enabled() and any(t.requires_grad for t in self.params[k]):
+            return torch.clamp_min(z + self.net(k, torch.cat([p, z], dim=1).contiguous()), 0.0)
+        x = torch.empty((p.shape[0], 2) + tuple(p.shape[2:]), dtype=torch.float32, device=p.device)
+        for b in range(p.shape[0]):
+            nn.axpby(p[b, 0].contiguous(), None, 1.0, out=x[b, 0])
+            nn.axpby(z[b, 0].contiguous(), None, 1.0, out=x[b, 1])
+        return nn.axpby(z.contiguous(), self.net(k, x), 1.0, 1.0, clamp0=True)
 
 
 def gradient_step(plan, f, p, eta):
-    """z = p - eta A^T C^T (C A p - f) for one volume [nz, ny, nx] (library operator)."""
+    """z = p - eta A^T C^T (C A p - f) for one volume [nz, ny, nx] (library operator and pat_axpby)."""
     r = torch.empty(plan.data_shape, dtype=torch.float32, device=p.device)
     P.pat_forward(plan, p.contiguous(), r)
-    r -= f
+    nn.axpby(r, f, 1.0, -1.0, out=r)
     g = torch.empty(plan.vol_shape, dtype=torch.float32, device=p.device)
     P.pat_adjoint(plan, r, g)
-    return p - eta * g
+    return nn.axpby(p.contiguous(), g, 1.0, -eta)
 
 
 def reconstruct(model, plan, f, L):

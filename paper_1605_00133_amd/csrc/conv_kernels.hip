@@ -507,6 +507,28 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float
 
 int nchunks(long rows) { return (int)(rows < kChunks ? rows : kChunks); }
 
+// The LDS weight gradient runs (chunk, tile group) blocks. With one tile group (narrow
+// layers: at most 32 output tiles) kChunks chunks leave one block per CU, too few to hide
+// its staging latency: such layers take kChunksNarrow chunks, four blocks per CU (16 -> 16
+// channels at 128^3: 1.86 -> 1.14 ms). Wider layers keep kChunks (with three tile groups,
+// 342 chunks were 30 % slower than 256: more partials to write and sum). Never more chunks
+// than row groups.
+constexpr long kChunksNarrow = 1024;
+
+bool wgrad_uses_lds(long rows, int cin, int cout) { return rows > 0 && cin <= kMaxChLds && cout <= kMaxChLds; }
+
+int wgrad_lds_tgroups(int cin, int cout) {
+  const int mtiles = (cout + 15) / 16, ntiles = (cin * kTaps + 1 + 15) / 16;
+  return (mtiles * ntiles + 4 * kWgTiles - 1) / (4 * kWgTiles);
+}
+
+int wgrad_lds_chunks(int batch, int cin, int cout, int nz, int ny) {
+  const long groups = (long)batch * nz * ((ny + kTileY - 1) / kTileY);
+  long nc = wgrad_lds_tgroups(cin, cout) == 1 ? kChunksNarrow : kChunks;
+  if (nc > groups) nc = groups;
+  return (int)(nc < 1 ? 1 : nc);
+}
+
 pat_status conv_args(const char* who, int nb, int cin, int cout, int nz, int ny, int nx) {
   if (nb < 0 || cin < 1 || cout < 1 || nz < 1 || ny < 1 || nx < 1)
     return pat::set_error(PAT_ERR_INVALID, "%s: sizes must be positive (batch >= 0)", who);
@@ -663,7 +685,8 @@ size_t pat_conv3d_backward_weight_workspace_bytes(int32_t batch, int32_t c_in, i
                                                   int32_t nx) {
   if (conv_args("pat_conv3d_backward_weight_workspace_bytes", batch, c_in, c_out, nz, ny, nx) != PAT_OK) return 0;
   const long rows = (long)batch * nz * ny;
-  const int nc = nchunks(rows < 1 ? 1 : rows);
+  const int nc = wgrad_uses_lds(rows, c_in, c_out) ? wgrad_lds_chunks(batch, c_in, c_out, nz, ny)
+                                                    : nchunks(rows < 1 ? 1 : rows);
   return (size_t)nc * c_out * (c_in * kTaps + 1) * sizeof(float);
 }
 
@@ -683,11 +706,10 @@ pat_status pat_conv3d_backward_weight(const float* x, const float* dy, float* dw
   const int ncw = ntiles >= 16 ? kWgCols : 1;
   const int ngroups = (ntiles + ncw - 1) / ncw;
   float* part = (float*)workspace;
-  if (rows > 0 && c_in <= kMaxChLds && c_out <= kMaxChLds) {
+  if (wgrad_uses_lds(rows, c_in, c_out)) {
     const int ytiles = (ny + kTileY - 1) / kTileY, xtiles = (nx + kTileX - 1) / kTileX;
-    const long groups = (long)batch * nz * ytiles;
-    nc = (int)(groups < kChunks ? groups : kChunks);   // <= nchunks(rows): fits the workspace
-    const int tgroups = (mtiles * ntiles + 4 * kWgTiles - 1) / (4 * kWgTiles);
+    nc = wgrad_lds_chunks(batch, c_in, c_out, nz, ny);   // the count the workspace was sized for
+    const int tgroups = wgrad_lds_tgroups(c_in, c_out);
     const size_t lds = ((size_t)mtiles * 16 * kTileY * kTileX + (size_t)c_in * 3 * kHaloY * kHaloX) * sizeof(short);
     hipLaunchKernelGGL(k_conv3d_wgrad_lds, dim3((unsigned)((long)nc * tgroups)), dim3(256), lds, (hipStream_t)stream, x,
                        dy, part, batch, c_in, c_out, nz, ny, nx, nc, mtiles, ntiles, tgroups, ytiles, xtiles);

@@ -43,9 +43,12 @@ def test_library_exports_every_nn_function():
 def test_nn_validation_without_gpu():
     from paper_1605_00133_amd import nn
     lib = nn.lib()
-    # K = 27 * 3 + 1 bias column, 2 * 5 * 6 = 60 rows -> 60 chunks
-    assert lib.pat_conv3d_backward_weight_workspace_bytes(2, 3, 20, 5, 6, 37) == 60 * 20 * 82 * 4
-    assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 16, 16, 128, 128, 128) == 256 * 16 * 433 * 4
+    # K = 27 * 3 + 1 bias column; the LDS weight gradient sums one partial per chunk of row groups:
+    # here every row group (2 batches x 5 planes x 2 groups of 4 rows) is a chunk
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(2, 3, 20, 5, 6, 37) == 20 * 20 * 82 * 4
+    # a narrow layer (one group of <= 32 output tiles: 1 x 28) takes 1024 chunks, a wider one 256
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 16, 16, 128, 128, 128) == 1024 * 16 * 433 * 4
+    assert lib.pat_conv3d_backward_weight_workspace_bytes(4, 24, 24, 32, 32, 32) == 256 * 24 * 649 * 4
     assert lib.pat_conv3d_backward_weight_workspace_bytes(1, 0, 16, 8, 8, 8) == 0
     # packed weights: ceil(co / 16) tiles x ceil(27 cpad / 32) chunks x 512 bfloat16, cpad = ci rounded up to 8
     assert lib.pat_conv3d_workspace_bytes(3, 20) == max(2 * 7 * 1024, 1 * 21 * 1024)

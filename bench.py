@@ -320,11 +320,11 @@ def main():
     src_hash = kernel_source_hash()
     traffic = measured_traffic(dom, src_hash)
     R, Cb = 4.0 * n ** 3, 8.0 * n * n * (n // 2 + 1)
-    survey_bytes = 20 * Cb + 12 * R     # one time step at two global passes per 3D FFT
+    fft_step_bytes = 20 * Cb + 12 * R     # one time step at two global passes per 3D FFT
     roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"],
-                "frac_of_3d_fft_step_bytes": round(survey_bytes / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "frac_of_3d_fft_step_bytes": round(fft_step_bytes / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                 "frac_of_copy_ceiling": round(dk["GBps"] / copy_GBps, 4)}
 
     err = fp64_error(P, torch, prob)

@@ -433,6 +433,32 @@ def bench_learned(prob, curve, log=None, n_steps=8, widths=(16, 32, 64), extra_s
     return out
 
 
+def evaluate_only(path, n=128, sampling="hadamard", n_steps=8, seeds=(5004,), repeats=2, log=None):
+    """The learned reconstruction of a saved model alone (no training, no TV+Br reference run): for
+    each phantom seed, `repeats` runs of reconstruct_with_fallback with its concurrent plain-FISTA
+    check (the first also loads code); returns per-seed PSNR, wall time of the last run, fallback
+    and residuals."""
+    from synthetic import gaussian_volume
+    dev = torch.device("cuda:0")
+    model = LearnedUNetRecon.load(path, dev)
+    model = model.truncated(min(n_steps, model.n_steps))
+    plan, ref_plan = make_plan(n, sampling), make_plan(n, sampling)
+    x0 = torch.from_numpy(gaussian_volume(plan.vol_shape, 8).astype(np.float32)).to(dev)
+    L = P.pat_power_iteration(plan, x0, 10)
+    rows = []
+    for seed in seeds:
+        case = make_case(plan, seed, sampling)
+        for _ in range(max(1, repeats)):
+            _, info = reconstruct_with_fallback(model, plan, case["f"], L, case["lam_tv"], case["lam_br"],
+                                                p_ref=case["p0"], ref_plan=ref_plan)
+        rows.append({"seed": seed, "n_steps": model.n_steps, **info})
+        if log:
+            log(f"phantom {seed}: {info['psnr_db']:.2f} dB in {info['ms']:.0f} ms, fallback {info['fallback']}")
+    ref_plan.close()
+    plan.close()
+    return rows
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="Train and evaluate the U-Net learned reconstruction.")
@@ -450,8 +476,17 @@ def main(argv=None):
     ap.add_argument("--eval-steps", default="", help="comma-separated step counts evaluated besides --steps")
     ap.add_argument("--init", default=None, help="safetensors model to continue training from")
     ap.add_argument("--train-seed0", type=int, default=1000, help="seed of the first training phantom")
+    ap.add_argument("--evaluate", default=None,
+                    help="evaluate this saved model ('default': the package's weights) on --seeds and exit")
+    ap.add_argument("--seeds", default="5004", help="phantom seeds of --evaluate (comma-separated)")
     a = ap.parse_args(argv)
     widths = tuple(int(w) for w in a.widths.split(","))
+    if a.evaluate:
+        path = weights_path(a.n, a.sampling, widths) if a.evaluate == "default" else a.evaluate
+        rows = evaluate_only(path, a.n, a.sampling, a.steps, tuple(int(x) for x in a.seeds.split(",") if x.strip()),
+                             log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps(rows), flush=True)
+        return
     save = weights_path(a.n, a.sampling, widths) if a.save == "default" else a.save
     ev = [int(k) for k in a.eval_steps.split(",") if k.strip()]
     out = experiment(a.n, a.sampling, a.train, a.test, a.steps, widths, a.epochs, a.batch, a.lr, a.workers, save,
